@@ -1,0 +1,205 @@
+/*
+ * dg.h -- C ABI of the MI355X nodal discontinuous-Galerkin Euler library.
+ *
+ * The library integrates the three-dimensional compressible Euler equations
+ * (Section 2.1, Eqs. 1-2) on a tetrahedral partition of the domain
+ * (Appendix A, Eq. 9) with a nodal DG discretization of the weak form
+ * (Appendix A, Eqs. 10-11), the local Lax-Friedrichs flux (Section 1.1) and a
+ * five-stage fourth-order low-storage Runge-Kutta scheme for the resulting
+ * ODE system dc/dt = f(c) (Appendix A, Eq. 12).  Boundary faces take the
+ * pass-through state (Section 2.2), a characteristic outflow state, the
+ * reflective wall (Section 2.3, Eq. 4), the mouthpiece inflow pulse
+ * (Section 2.4, Eqs. 5-7) or a learned closure.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns int: DG_OK (0) or a negative DG_E* code; the message
+ *   of the last failure is available from dg_last_error(ctx) (or
+ *   dg_last_error(NULL) when no context could be created).
+ * - "host" pointers are ordinary CPU memory, read during the call only;
+ *   "device" pointers are GPU global memory (hipMalloc or torch tensors)
+ *   owned by the caller, 16-byte aligned, never retained after the call.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Device work is enqueued asynchronously on it unless a call says
+ *   otherwise.  Calls on one context must not overlap in time; a context is
+ *   not safe for concurrent host threads.
+ * - State layout: FP32 [K][5][Np], element-major, variables in the order
+ *   (rho, rho u, rho v, rho w, E), nodes in the library's own order (use
+ *   dg_nodes for their coordinates).  The stored values are the PERTURBATION
+ *   of the conserved variables about the ambient state set at setup,
+ *   q' = q - q0; the right-hand side of q' equals that of q.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------ */
+#define DG_OK 0
+#define DG_EINVAL (-1)    /* bad argument (null pointer, N, K, tag, flag)      */
+#define DG_EMESH (-2)     /* invalid mesh (degenerate element, bad face match)  */
+#define DG_ENOMEM (-3)    /* host or device allocation failed                  */
+#define DG_EHIP (-4)      /* a HIP runtime call failed                         */
+#define DG_ENONPHYS (-5)  /* rho <= 0, p <= 0 or NaN reached during dg_run     */
+#define DG_ENODEV (-6)    /* device call on a context created host-only        */
+
+/* ---- boundary tags (per element face) ---------------------------------- */
+#define DG_BC_INTERIOR 0     /* matched to a neighbour                          */
+#define DG_BC_OUTFLOW_CHAR 1 /* incoming acoustic characteristic set to ambient */
+#define DG_BC_PASSTHRU 2     /* ghost = ambient rest state (Section 2.2)        */
+#define DG_BC_WALL 3         /* slip wall, v - 2(v.n)n (Section 2.3, Eq. 4)      */
+#define DG_BC_INFLOW 4       /* mouthpiece pulse (Section 2.4, Eqs. 5-7)         */
+#define DG_BC_LEARNED 5      /* learned closure; characteristic outflow when no
+                                network is attached                            */
+
+/* ---- precision forms ---------------------------------------------------- */
+#define DG_FP32 0        /* FP32 state, fluxes and contractions              */
+#define DG_SPLIT_BF16 1  /* volume contraction as three BF16 MFMA products
+                            (hi*hi + hi*lo + lo*hi), FP32 accumulation       */
+
+/* ---- setup flags -------------------------------------------------------- */
+#define DG_SETUP_HOST_ONLY 1 /* build host data only (no GPU needed); device
+                                calls then return DG_ENODEV                  */
+
+typedef struct dg_ctx dg_ctx;
+
+/*
+ * Mesh and problem description for dg_mesh_setup.
+ *
+ * N        polynomial order, 1..5.
+ * K        number of tetrahedra, > 0.
+ * xyz      host double [K][4][3]: coordinates of each element's vertices.
+ * EToV     host int64 [K][4]: topological vertex ids; two faces are the same
+ *          face when their id triples agree (periodic images share ids).
+ * bc       host int8 [K][4]: tag of local face f, with f0={v0,v1,v2},
+ *          f1={v0,v1,v3}, f2={v1,v2,v3}, f3={v0,v2,v3}.  A face listed by two
+ *          elements is interior when both tags are DG_BC_INTERIOR and a
+ *          two-sided boundary (zero-thickness wall) when both are non-zero.
+ * gamma, rho0, u0, p0   ideal-gas ratio and ambient state (Section 2.2,
+ *          Eq. 3 uses rho0 = 1.4, p0 = 1; any consistent scaling works).
+ * inflow_amp, inflow_alpha   pulse p0 + amp (1 - cos(alpha t))/2 for
+ *          0 <= t < 2 pi/alpha on DG_BC_INFLOW faces (Section 2.4).
+ * precision  DG_FP32 or DG_SPLIT_BF16.
+ * flags    0 or DG_SETUP_HOST_ONLY.
+ */
+typedef struct dg_mesh_desc {
+  int32_t N;
+  int32_t precision;
+  int64_t K;
+  const double* xyz;
+  const int64_t* EToV;
+  const int8_t* bc;
+  double gamma;
+  double rho0;
+  double u0[3];
+  double p0;
+  double inflow_amp;
+  double inflow_alpha;
+  int32_t flags;
+  int32_t reserved;
+} dg_mesh_desc;
+
+/*
+ * Build a context: orientation fix (an element with negative Jacobian has
+ * its local vertices 1 and 2 swapped, which exchanges the tags of faces 1
+ * and 3), face matching, nodes, reference operators and affine geometry in
+ * FP64 (Appendix A, Eqs. 9-11), then upload to the current HIP device.
+ * Synchronous.  Host arrays are copied.  Errors: DG_EINVAL, DG_EMESH,
+ * DG_ENOMEM, DG_EHIP; *out is NULL on failure.
+ */
+int dg_mesh_setup(const dg_mesh_desc* d, void* stream, dg_ctx** out);
+
+/* Free a context and all device memory it owns.  NULL is accepted. */
+int dg_destroy(dg_ctx* ctx);
+
+/* Message of the last failure on ctx (or of the last failed setup when
+ * ctx is NULL).  The string lives until the next call on the same ctx. */
+const char* dg_last_error(const dg_ctx* ctx);
+
+/* Sizes: nodes per element, nodes per face, elements. */
+int dg_sizes(const dg_ctx* ctx, int32_t* Np, int32_t* Nfp, int64_t* K);
+
+/* Physical coordinates of every node, host double [K][Np][3], in the
+ * library's node order and after the orientation fix. */
+int dg_nodes(const dg_ctx* ctx, double* xyz_out);
+
+/*
+ * Host copies of the setup products (FP64), for checking the setup against
+ * an independent construction.  Any pointer may be NULL.
+ *   rst     [Np][3]           reference node coordinates
+ *   Dr,Ds,Dt [Np][Np]         nodal differentiation matrices
+ *   LIFT    [Np][4*Nfp]       M^-1 times the face mass matrices
+ *   Fmask   int32 [4][Nfp]    node index of each face node
+ */
+int dg_reference_operators(const dg_ctx* ctx, double* rst, double* Dr, double* Ds,
+                           double* Dt, double* LIFT, int32_t* Fmask);
+
+/*
+ *   drst_dx [K][3][3]   d(r,s,t)/d(x,y,z) per element
+ *   J       [K]         Jacobian determinant of the reference map
+ *   nrm     [K][4][3]   outward unit normal of each face
+ *   Fscale  [K][4]      surface-to-volume Jacobian ratio sJ/J
+ *   mapP    int64 [K][4][Nfp]  k'*Np + node of the neighbour node at the
+ *                       same point, or -1 on boundary faces
+ */
+int dg_geometry(const dg_ctx* ctx, double* drst_dx, double* J, double* nrm,
+                double* Fscale, int64_t* mapP);
+
+/*
+ * f(q) of Appendix A, Eq. 12: rhs = -(Dr Fr + Ds Fs + Dt Ft)
+ * + sum_f Fscale_f LIFT_f dF_f at time t (t enters through inflow faces).
+ * q, rhs: device FP32 [K][5][Np] perturbation states (see conventions).
+ * Asynchronous on stream; no allocation.
+ */
+int dg_rhs(dg_ctx* ctx, const float* q, float* rhs, double t, void* stream);
+
+/*
+ * One five-stage low-storage RK step of size dt starting at time t:
+ * for i = 1..5: res = a_i res + dt f(q, t + c_i dt); q = q + b_i res.
+ * q (in/out) and res (scratch, contents ignored on entry since a_1 = 0):
+ * device FP32 [K][5][Np].  Asynchronous on stream; no allocation.
+ */
+int dg_step(dg_ctx* ctx, float* q, float* res, double t, double dt, void* stream);
+
+/*
+ * nsteps steps with dt = cfl / max over elements, faces and face nodes of
+ * (N+1)^2/2 * Fscale * (|u| + c), recomputed on the device at the start of
+ * every step from the interior face traces.  The step sequence is captured
+ * once in a HIP graph and replayed.  *t_inout is the start time on entry and
+ * the end time on return; *dt_last (may be NULL) receives the last dt.
+ * Synchronizes the stream once at the end.  Returns DG_ENONPHYS when a
+ * non-physical state (rho <= 0, p <= 0 or NaN in a face trace) was seen;
+ * dg_last_step then gives the first such step and the state is that of the
+ * end of the run.
+ */
+int dg_run(dg_ctx* ctx, float* q, float* res, int64_t nsteps, double cfl,
+           double* t_inout, double* dt_last, void* stream);
+
+/* Step index (0-based, within the last dg_run) of the first non-physical
+ * state, or -1. */
+int64_t dg_last_step(const dg_ctx* ctx);
+
+/* dt of the CFL rule above for state q, written to *dt (host).
+ * Synchronizes the stream. */
+int dg_stable_dt(dg_ctx* ctx, const float* q, double cfl, double* dt, void* stream);
+
+/*
+ * Convert primitive fields (rho, u, v, w, p) at the nodes, device FP32
+ * [K][5][Np] given as perturbations about the ambient state
+ * (rho - rho0, u - u0, v - v0, w - w0, p - p0), into the conserved
+ * perturbation state q' of the same layout (Eq. 2).
+ */
+int dg_prim_to_state(dg_ctx* ctx, const float* prim, float* q, void* stream);
+
+/* Inverse of dg_prim_to_state. */
+int dg_state_to_prim(dg_ctx* ctx, const float* q, float* prim, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H */

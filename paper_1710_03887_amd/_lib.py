@@ -1,0 +1,245 @@
+"""ctypes binding of libdg.so with the same names as the C ABI (include/dg.h).
+
+Only argument marshalling happens here: numpy arrays become host pointers,
+torch tensors become device pointers, torch streams become hipStream_t.
+Every step of the method runs in the library's HIP kernels; there is no
+fallback: if the library is missing, importing this module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("DG_LIBRARY", os.path.join(HERE, "libdg.so"))
+
+DG_OK, DG_EINVAL, DG_EMESH, DG_ENOMEM, DG_EHIP, DG_ENONPHYS, DG_ENODEV = 0, -1, -2, -3, -4, -5, -6
+DG_BC_INTERIOR, DG_BC_OUTFLOW_CHAR, DG_BC_PASSTHRU, DG_BC_WALL, DG_BC_INFLOW, DG_BC_LEARNED = range(6)
+DG_FP32, DG_SPLIT_BF16 = 0, 1
+DG_SETUP_HOST_ONLY = 1
+
+_ERRNAMES = {DG_EINVAL: "DG_EINVAL", DG_EMESH: "DG_EMESH", DG_ENOMEM: "DG_ENOMEM",
+             DG_EHIP: "DG_EHIP", DG_ENONPHYS: "DG_ENONPHYS", DG_ENODEV: "DG_ENODEV"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1710_03887_amd.build`")
+# torch carries its own HIP runtime under the same soname (libamdhip64.so.7);
+# loading torch first makes libdg.so bind to that one, so that the library
+# and torch's tensors and streams share a single runtime in the process.
+import torch  # noqa: E402,F401
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp = ctypes.c_void_p
+_i32, _i64, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+
+class dg_mesh_desc(ctypes.Structure):
+    _fields_ = [("N", _i32), ("precision", _i32), ("K", _i64),
+                ("xyz", _vp), ("EToV", _vp), ("bc", _vp),
+                ("gamma", _f64), ("rho0", _f64), ("u0", _f64 * 3), ("p0", _f64),
+                ("inflow_amp", _f64), ("inflow_alpha", _f64),
+                ("flags", _i32), ("reserved", _i32)]
+
+
+_SIGS = {
+    "dg_mesh_setup": (ctypes.c_int, [ctypes.POINTER(dg_mesh_desc), _vp, ctypes.POINTER(_vp)]),
+    "dg_destroy": (ctypes.c_int, [_vp]),
+    "dg_last_error": (ctypes.c_char_p, [_vp]),
+    "dg_sizes": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64)]),
+    "dg_nodes": (ctypes.c_int, [_vp, _vp]),
+    "dg_reference_operators": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "dg_geometry": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "dg_rhs": (ctypes.c_int, [_vp, _vp, _vp, _f64, _vp]),
+    "dg_step": (ctypes.c_int, [_vp, _vp, _vp, _f64, _f64, _vp]),
+    "dg_run": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, ctypes.POINTER(_f64),
+                              ctypes.POINTER(_f64), _vp]),
+    "dg_last_step": (_i64, [_vp]),
+    "dg_stable_dt": (ctypes.c_int, [_vp, _vp, _f64, ctypes.POINTER(_f64), _vp]),
+    "dg_prim_to_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "dg_state_to_prim": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+class DGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code, handle):
+    if code != DG_OK:
+        msg = _lib.dg_last_error(handle)
+        raise DGError(code, msg.decode() if msg else "")
+
+
+def _ptr(x):
+    """Device pointer of a torch tensor, or host pointer of a numpy array."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr()
+    raise TypeError(f"cannot pass {type(x)}")
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available() and torch.cuda.is_initialized():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:  # torch absent or no device: default stream
+            pass
+        return None
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _check_state(ctx, x, name):
+    if x is None:
+        raise ValueError(f"{name} is None")
+    shape = (ctx.K, 5, ctx.Np)
+    if tuple(x.shape) != shape:
+        raise ValueError(f"{name} has shape {tuple(x.shape)}, expected {shape}")
+    if str(getattr(x, "dtype", "")) not in ("torch.float32", "float32"):
+        raise ValueError(f"{name} must be float32")
+    if not getattr(x, "is_cuda", False):
+        raise ValueError(f"{name} must be a device tensor")
+
+
+class Context:
+    """Owns a dg_ctx handle; freed by dg_destroy."""
+
+    def __init__(self, handle, N):
+        self.handle = handle
+        self.N = N
+        Np, Nfp, K = _i32(), _i32(), _i64()
+        _check(_lib.dg_sizes(handle, ctypes.byref(Np), ctypes.byref(Nfp), ctypes.byref(K)), handle)
+        self.Np, self.Nfp, self.K = Np.value, Nfp.value, K.value
+
+    def close(self):
+        if self.handle:
+            _lib.dg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dg_mesh_setup(xyz, EToV, bc, N, gamma=1.4, rho0=1.0, u0=(0.0, 0.0, 0.0), p0=1.0 / 1.4,
+                  precision=DG_FP32, inflow_amp=0.0, inflow_alpha=2 * np.pi * 565.0 / 343.0,
+                  host_only=False, stream=None):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    EToV = np.ascontiguousarray(EToV, dtype=np.int64)
+    bc = np.ascontiguousarray(bc, dtype=np.int8)
+    K = xyz.shape[0]
+    if xyz.shape != (K, 4, 3) or EToV.shape != (K, 4) or bc.shape != (K, 4):
+        raise ValueError("mesh arrays must be xyz[K,4,3], EToV[K,4], bc[K,4]")
+    d = dg_mesh_desc(N=N, precision=precision, K=K, xyz=xyz.ctypes.data, EToV=EToV.ctypes.data,
+                     bc=bc.ctypes.data, gamma=gamma, rho0=rho0, u0=(_f64 * 3)(*u0), p0=p0,
+                     inflow_amp=inflow_amp, inflow_alpha=inflow_alpha,
+                     flags=DG_SETUP_HOST_ONLY if host_only else 0, reserved=0)
+    h = _vp()
+    _check(_lib.dg_mesh_setup(ctypes.byref(d), None if host_only else _stream(stream),
+                              ctypes.byref(h)), None)
+    return Context(h, N)
+
+
+def dg_destroy(ctx):
+    ctx.close()
+
+
+def dg_last_error(ctx=None):
+    msg = _lib.dg_last_error(ctx.handle if ctx else None)
+    return msg.decode() if msg else ""
+
+
+def dg_sizes(ctx):
+    return ctx.Np, ctx.Nfp, ctx.K
+
+
+def dg_nodes(ctx):
+    out = np.empty((ctx.K, ctx.Np, 3))
+    _check(_lib.dg_nodes(ctx.handle, _ptr(out)), ctx.handle)
+    return out
+
+
+def dg_reference_operators(ctx):
+    Np, Nfp = ctx.Np, ctx.Nfp
+    rst = np.empty((Np, 3))
+    Dr, Ds, Dt = (np.empty((Np, Np)) for _ in range(3))
+    LIFT = np.empty((Np, 4 * Nfp))
+    Fmask = np.empty((4, Nfp), dtype=np.int32)
+    _check(_lib.dg_reference_operators(ctx.handle, *(_ptr(a) for a in (rst, Dr, Ds, Dt, LIFT, Fmask))),
+           ctx.handle)
+    return {"rst": rst, "Dr": Dr, "Ds": Ds, "Dt": Dt, "LIFT": LIFT, "Fmask": Fmask}
+
+
+def dg_geometry(ctx):
+    K, Nfp = ctx.K, ctx.Nfp
+    g = {"drst_dx": np.empty((K, 3, 3)), "J": np.empty(K), "nrm": np.empty((K, 4, 3)),
+         "Fscale": np.empty((K, 4)), "mapP": np.empty((K, 4, Nfp), dtype=np.int64)}
+    _check(_lib.dg_geometry(ctx.handle, *(_ptr(g[k]) for k in ("drst_dx", "J", "nrm", "Fscale", "mapP"))),
+           ctx.handle)
+    return g
+
+
+def dg_rhs(ctx, q, rhs, t=0.0, stream=None):
+    _check_state(ctx, q, "q")
+    _check_state(ctx, rhs, "rhs")
+    _check(_lib.dg_rhs(ctx.handle, _ptr(q), _ptr(rhs), float(t), _stream(stream)), ctx.handle)
+
+
+def dg_step(ctx, q, res, t, dt, stream=None):
+    _check_state(ctx, q, "q")
+    _check_state(ctx, res, "res")
+    _check(_lib.dg_step(ctx.handle, _ptr(q), _ptr(res), float(t), float(dt), _stream(stream)),
+           ctx.handle)
+
+
+def dg_run(ctx, q, res, nsteps, cfl, t=0.0, stream=None):
+    """Returns (t_end, dt_last).  Raises DGError(DG_ENONPHYS) on a
+    non-physical state; dg_last_step(ctx) then names the first such step."""
+    _check_state(ctx, q, "q")
+    _check_state(ctx, res, "res")
+    tt, dl = _f64(t), _f64(0.0)
+    _check(_lib.dg_run(ctx.handle, _ptr(q), _ptr(res), int(nsteps), float(cfl), ctypes.byref(tt),
+                       ctypes.byref(dl), _stream(stream)), ctx.handle)
+    return tt.value, dl.value
+
+
+def dg_last_step(ctx):
+    return int(_lib.dg_last_step(ctx.handle))
+
+
+def dg_stable_dt(ctx, q, cfl, stream=None):
+    _check_state(ctx, q, "q")
+    dt = _f64()
+    _check(_lib.dg_stable_dt(ctx.handle, _ptr(q), float(cfl), ctypes.byref(dt), _stream(stream)),
+           ctx.handle)
+    return dt.value
+
+
+def dg_prim_to_state(ctx, prim, q, stream=None):
+    _check_state(ctx, prim, "prim")
+    _check_state(ctx, q, "q")
+    _check(_lib.dg_prim_to_state(ctx.handle, _ptr(prim), _ptr(q), _stream(stream)), ctx.handle)
+
+
+def dg_state_to_prim(ctx, q, prim, stream=None):
+    _check_state(ctx, q, "q")
+    _check_state(ctx, prim, "prim")
+    _check(_lib.dg_state_to_prim(ctx.handle, _ptr(q), _ptr(prim), _stream(stream)), ctx.handle)

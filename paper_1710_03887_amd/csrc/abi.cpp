@@ -1,0 +1,421 @@
+// C ABI of the nodal DG Euler library: context setup, uploads, launches and
+// the HIP-graph-captured run loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dg.h"
+#include "kernels.hpp"
+#include "setup.hpp"
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+// Five-stage low-storage RK coefficients (Carpenter & Kennedy 1994).
+const double kRK4a[5] = {0.0, -567301805773.0 / 1357537059087.0,
+                         -2404267990393.0 / 2016746695238.0, -3550918686646.0 / 2091501179385.0,
+                         -1275806237668.0 / 842570457699.0};
+const double kRK4b[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                         1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                         2277821191437.0 / 14882151754819.0};
+const double kRK4c[5] = {0.0, 1432997174477.0 / 9575080441755.0,
+                         2526269341429.0 / 6820363962896.0, 2006345519317.0 / 3224310063776.0,
+                         2802321613138.0 / 2924317926251.0};
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  const float* q = nullptr;
+  const float* res = nullptr;
+};
+
+}  // namespace
+
+struct dg_ctx {
+  std::string err;
+  bool host_only = false;
+  dg::RefOps ops;
+  dg::HostMesh mesh;
+  dg::DeviceMesh dm;
+  std::vector<void*> allocs;
+  float* qbuf = nullptr;            // ping-pong partner of the caller's state
+  dg::RunScalars* run = nullptr;    // device scalars
+  dg::RunScalars host_run{};        // staging for uploads/downloads
+  hipStream_t capture_stream = nullptr;
+  GraphCache two_steps;
+  int64_t last_bad = -1;
+};
+
+namespace {
+
+int fail(dg_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_setup_error = msg;
+  return code;
+}
+
+int hip_fail(dg_ctx* c, hipError_t e, const char* what) {
+  return fail(c, DG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+int upload(dg_ctx* c, const T* host, size_t n, T** dev, hipStream_t s) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(T) + 16);
+  if (e != hipSuccess) return fail(c, DG_ENOMEM, "hipMalloc failed");
+  c->allocs.push_back(p);
+  if (host) {
+    e = hipMemcpyAsync(p, host, n * sizeof(T), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  }
+  *dev = static_cast<T*>(p);
+  return DG_OK;
+}
+
+void free_device(dg_ctx* c) {
+  if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
+  c->two_steps = GraphCache{};
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+  c->capture_stream = nullptr;
+}
+
+int need_device(dg_ctx* c) {
+  if (!c) return fail(nullptr, DG_EINVAL, "null context");
+  if (c->host_only) return fail(c, DG_ENODEV, "context was created host-only");
+  return DG_OK;
+}
+
+int build_device(dg_ctx* c, hipStream_t s) {
+  const auto& ops = c->ops;
+  const auto& mh = c->mesh;
+  const int Np = ops.Np, Nfp = ops.Nfp;
+  const int64_t K = mh.K;
+  const int KT = 3 * Np + 4 * Nfp, KT4 = (KT + 3) / 4 * 4, MP = (Np + 15) / 16 * 16;
+
+  // contraction operator A = [-Dr -Ds -Dt LIFT], stored transposed and
+  // zero-padded: Aop[k][m] = A[m][k]
+  std::vector<float> Aop(size_t(KT4) * MP, 0.0f);
+  for (int mrow = 0; mrow < Np; ++mrow)
+    for (int k = 0; k < KT; ++k) {
+      double v;
+      if (k < Np) v = -ops.Dr[size_t(mrow) * Np + k];
+      else if (k < 2 * Np) v = -ops.Ds[size_t(mrow) * Np + k - Np];
+      else if (k < 3 * Np) v = -ops.Dt[size_t(mrow) * Np + k - 2 * Np];
+      else v = ops.LIFT[size_t(mrow) * 4 * Nfp + k - 3 * Np];
+      Aop[size_t(k) * MP + mrow] = float(v);
+    }
+  std::vector<uint8_t> fmask(size_t(4) * Nfp);
+  for (size_t i = 0; i < fmask.size(); ++i) fmask[i] = uint8_t(ops.Fmask[i]);
+  std::vector<double> sgeo(size_t(K) * 16);
+  for (int64_t k = 0; k < K; ++k)
+    for (int f = 0; f < 4; ++f) {
+      for (int d = 0; d < 3; ++d) sgeo[size_t(k) * 16 + f * 4 + d] = mh.nrm[size_t(k) * 12 + f * 3 + d];
+      sgeo[size_t(k) * 16 + f * 4 + 3] = mh.Fscale[size_t(k) * 4 + f];
+    }
+  std::vector<int32_t> nbr(size_t(K) * 4);
+  std::vector<uint8_t> finfo(size_t(K) * 4);
+  for (size_t i = 0; i < nbr.size(); ++i) {
+    nbr[i] = mh.EToE[i] >= 0 ? mh.EToE[i] : -int32_t(mh.bc[i]);
+    finfo[i] = uint8_t(mh.EToF[i] | (mh.orient[i] << 2));
+  }
+
+  hipError_t e = dg::prepare_kernels(c->dm.N);
+  if (e != hipSuccess) return hip_fail(c, e, "hipFuncSetAttribute");
+  e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamCreate");
+
+  float* dA;
+  uint8_t *dF, *dNN, *dFi;
+  double *dV, *dS;
+  int32_t* dN;
+  int rc;
+  if ((rc = upload(c, Aop.data(), Aop.size(), &dA, s))) return rc;
+  if ((rc = upload(c, fmask.data(), fmask.size(), &dF, s))) return rc;
+  if ((rc = upload(c, ops.nbr_node.data(), ops.nbr_node.size(), &dNN, s))) return rc;
+  if ((rc = upload(c, mh.drst_dx.data(), mh.drst_dx.size(), &dV, s))) return rc;
+  if ((rc = upload(c, sgeo.data(), sgeo.size(), &dS, s))) return rc;
+  if ((rc = upload(c, nbr.data(), nbr.size(), &dN, s))) return rc;
+  if ((rc = upload(c, finfo.data(), finfo.size(), &dFi, s))) return rc;
+  if ((rc = upload<float>(c, nullptr, size_t(K) * 5 * Np, &c->qbuf, s))) return rc;
+  if ((rc = upload<dg::RunScalars>(c, nullptr, 1, &c->run, s))) return rc;
+  c->host_run = dg::RunScalars{};
+  c->host_run.first_bad = -1;
+  e = hipMemcpyAsync(c->run, &c->host_run, sizeof(dg::RunScalars), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+
+  c->dm.Aop = dA;
+  c->dm.fmask = dF;
+  c->dm.nbr_node = dNN;
+  c->dm.vgeo = dV;
+  c->dm.sgeo = dS;
+  c->dm.nbr = dN;
+  c->dm.finfo = dFi;
+  return DG_OK;
+}
+
+// Enqueue one LSERK step on `s` with state ping-ponging between q and the
+// context buffer; returns with the state in q when `end_in_q`, which needs
+// an even number of stage swaps in total (handled by the caller).
+hipError_t enqueue_stages(dg_ctx* c, float* q, float* res, bool start_in_q, double t, double dt,
+                          const dg::RunScalars* run, hipStream_t s) {
+  float* bufs[2] = {q, c->qbuf};
+  int cur = start_in_q ? 0 : 1;
+  for (int i = 0; i < 5; ++i) {
+    hipError_t e = dg::launch_stage(c->dm, dg::MODE_STAGE, bufs[cur], bufs[1 - cur], res, nullptr,
+                                    float(kRK4a[i]), float(kRK4b[i]), kRK4c[i], t, dt, run, s);
+    if (e != hipSuccess) return e;
+    cur = 1 - cur;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_mesh_setup(const dg_mesh_desc* d, void* stream, dg_ctx** out) {
+  if (!out) return fail(nullptr, DG_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!d || !d->xyz || !d->EToV || !d->bc) return fail(nullptr, DG_EINVAL, "null mesh array");
+  if (d->N < 1 || d->N > 5) return fail(nullptr, DG_EINVAL, "N must be in 1..5");
+  if (d->K <= 0) return fail(nullptr, DG_EINVAL, "K must be positive");
+  if (d->precision != DG_FP32 && d->precision != DG_SPLIT_BF16)
+    return fail(nullptr, DG_EINVAL, "unknown precision");
+  if ((d->flags & ~DG_SETUP_HOST_ONLY) != 0) return fail(nullptr, DG_EINVAL, "unknown flags");
+  if (!(d->gamma > 1.0) || !(d->rho0 > 0.0) || !(d->p0 > 0.0))
+    return fail(nullptr, DG_EINVAL, "need gamma > 1, rho0 > 0, p0 > 0");
+
+  dg_ctx* c = new (std::nothrow) dg_ctx;
+  if (!c) return fail(nullptr, DG_ENOMEM, "out of host memory");
+  std::string msg = dg::build_reference(d->N, c->ops);
+  if (msg.empty()) msg = dg::build_mesh(c->ops, d->K, d->xyz, d->EToV, d->bc, c->mesh);
+  if (!msg.empty()) {
+    delete c;
+    const bool arg = msg.find("tag") != std::string::npos && msg.find("unknown") != std::string::npos;
+    return fail(nullptr, arg ? DG_EINVAL : DG_EMESH, msg);
+  }
+  c->host_only = (d->flags & DG_SETUP_HOST_ONLY) != 0;
+  c->dm.N = d->N;
+  c->dm.Np = c->ops.Np;
+  c->dm.Nfp = c->ops.Nfp;
+  c->dm.K = d->K;
+  c->dm.precision = d->precision;
+  dg::Phys& P = c->dm.phys;
+  P.gamma = float(d->gamma);
+  P.gm1 = float(d->gamma - 1.0);
+  P.rho0 = float(d->rho0);
+  P.p0 = float(d->p0);
+  const double c0 = std::sqrt(d->gamma * d->p0 / d->rho0);
+  P.c0 = float(c0);
+  P.Z0 = float(d->rho0 * c0);
+  P.inv_c0sq = float(1.0 / (c0 * c0));
+  double u2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    P.u0[k] = float(d->u0[k]);
+    P.m0[k] = float(d->rho0 * d->u0[k]);
+    u2 += d->u0[k] * d->u0[k];
+  }
+  P.E0 = float(d->p0 / (d->gamma - 1.0) + 0.5 * d->rho0 * u2);
+  P.amp = float(d->inflow_amp);
+  P.alpha = d->inflow_alpha > 0.0 ? d->inflow_alpha : 1.0;
+  P.half_N1sq = float(0.5 * (d->N + 1) * (d->N + 1));
+  if (!c->host_only) {
+    const int rc = build_device(c, static_cast<hipStream_t>(stream));
+    if (rc) {
+      g_setup_error = c->err;
+      free_device(c);
+      delete c;
+      return rc;
+    }
+  }
+  *out = c;
+  return DG_OK;
+}
+
+int dg_destroy(dg_ctx* c) {
+  if (!c) return DG_OK;
+  free_device(c);
+  delete c;
+  return DG_OK;
+}
+
+const char* dg_last_error(const dg_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+int dg_sizes(const dg_ctx* c, int32_t* Np, int32_t* Nfp, int64_t* K) {
+  if (!c) return fail(nullptr, DG_EINVAL, "null context");
+  if (Np) *Np = c->ops.Np;
+  if (Nfp) *Nfp = c->ops.Nfp;
+  if (K) *K = c->mesh.K;
+  return DG_OK;
+}
+
+int dg_nodes(const dg_ctx* c, double* xyz_out) {
+  if (!c || !xyz_out) return fail(const_cast<dg_ctx*>(c), DG_EINVAL, "null argument");
+  dg::node_coordinates(c->ops, c->mesh, xyz_out);
+  return DG_OK;
+}
+
+int dg_reference_operators(const dg_ctx* c, double* rst, double* Dr, double* Ds, double* Dt,
+                           double* LIFT, int32_t* Fmask) {
+  if (!c) return fail(nullptr, DG_EINVAL, "null context");
+  const auto& o = c->ops;
+  if (rst) std::memcpy(rst, o.rst.data(), o.rst.size() * sizeof(double));
+  if (Dr) std::memcpy(Dr, o.Dr.data(), o.Dr.size() * sizeof(double));
+  if (Ds) std::memcpy(Ds, o.Ds.data(), o.Ds.size() * sizeof(double));
+  if (Dt) std::memcpy(Dt, o.Dt.data(), o.Dt.size() * sizeof(double));
+  if (LIFT) std::memcpy(LIFT, o.LIFT.data(), o.LIFT.size() * sizeof(double));
+  if (Fmask) std::memcpy(Fmask, o.Fmask.data(), o.Fmask.size() * sizeof(int32_t));
+  return DG_OK;
+}
+
+int dg_geometry(const dg_ctx* c, double* drst_dx, double* J, double* nrm, double* Fscale,
+                int64_t* mapP) {
+  if (!c) return fail(nullptr, DG_EINVAL, "null context");
+  const auto& m = c->mesh;
+  if (drst_dx) std::memcpy(drst_dx, m.drst_dx.data(), m.drst_dx.size() * sizeof(double));
+  if (J) std::memcpy(J, m.J.data(), m.J.size() * sizeof(double));
+  if (nrm) std::memcpy(nrm, m.nrm.data(), m.nrm.size() * sizeof(double));
+  if (Fscale) std::memcpy(Fscale, m.Fscale.data(), m.Fscale.size() * sizeof(double));
+  if (mapP) dg::neighbour_map(c->ops, m, mapP);
+  return DG_OK;
+}
+
+int dg_rhs(dg_ctx* c, const float* q, float* rhs, double t, void* stream) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (!q || !rhs) return fail(c, DG_EINVAL, "null state pointer");
+  hipError_t e = dg::launch_stage(c->dm, dg::MODE_RHS, q, nullptr, nullptr, rhs, 0.f, 0.f, 0.0, t,
+                                  0.0, nullptr, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DG_OK : hip_fail(c, e, "stage launch");
+}
+
+int dg_step(dg_ctx* c, float* q, float* res, double t, double dt, void* stream) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (!q || !res) return fail(c, DG_EINVAL, "null state pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = enqueue_stages(c, q, res, true, t, dt, nullptr, s);
+  if (e != hipSuccess) return hip_fail(c, e, "stage launch");
+  // five stages end in the context buffer
+  e = hipMemcpyAsync(q, c->qbuf, size_t(c->dm.K) * 5 * c->dm.Np * sizeof(float),
+                     hipMemcpyDeviceToDevice, s);
+  return e == hipSuccess ? DG_OK : hip_fail(c, e, "hipMemcpyAsync");
+}
+
+int dg_stable_dt(dg_ctx* c, const float* q, double cfl, double* dt, void* stream) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (!q || !dt) return fail(c, DG_EINVAL, "null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  c->host_run = dg::RunScalars{};
+  c->host_run.cfl = cfl;
+  c->host_run.first_bad = -1;
+  hipError_t e = hipMemcpyAsync(c->run, &c->host_run, sizeof(dg::RunScalars),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = dg::launch_rate(c->dm, q, c->run, s);
+  if (e == hipSuccess) e = dg::launch_finalize(c->run, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&c->host_run, c->run, sizeof(dg::RunScalars), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "dg_stable_dt");
+  *dt = c->host_run.dt;
+  if (c->host_run.first_bad >= 0) return fail(c, DG_ENONPHYS, "non-physical state");
+  return DG_OK;
+}
+
+int dg_run(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double* t_inout,
+           double* dt_last, void* stream) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (!q || !res || !t_inout) return fail(c, DG_EINVAL, "null argument");
+  if (nsteps < 0 || !(cfl > 0.0)) return fail(c, DG_EINVAL, "need nsteps >= 0 and cfl > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  c->host_run = dg::RunScalars{};
+  c->host_run.t = *t_inout;
+  c->host_run.cfl = cfl;
+  c->host_run.first_bad = -1;
+  hipError_t e = hipMemcpyAsync(c->run, &c->host_run, sizeof(dg::RunScalars),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+
+  // a graph of two steps (ten stage swaps) leaves the state in q
+  if (nsteps >= 2 && (c->two_steps.q != q || c->two_steps.res != res || !c->two_steps.exec)) {
+    if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
+    c->two_steps = GraphCache{};
+    hipStream_t cs = c->capture_stream;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < 2 && le == hipSuccess; ++k) {
+      const float* qs = (k == 0) ? q : c->qbuf;
+      le = dg::launch_rate(c->dm, qs, c->run, cs);
+      if (le == hipSuccess) le = dg::launch_finalize(c->run, cs);
+      if (le == hipSuccess) le = enqueue_stages(c, q, res, k == 0, 0.0, 0.0, c->run, cs);
+      if (le == hipSuccess) le = dg::launch_advance(c->run, cs);
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (le != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(c, le, "launch during capture");
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+    c->two_steps.exec = ex;
+    c->two_steps.q = q;
+    c->two_steps.res = res;
+  }
+  for (int64_t k = 0; k + 1 < nsteps; k += 2) {
+    e = hipGraphLaunch(c->two_steps.exec, s);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+  }
+  if (nsteps % 2 == 1) {
+    e = dg::launch_rate(c->dm, q, c->run, s);
+    if (e == hipSuccess) e = dg::launch_finalize(c->run, s);
+    if (e == hipSuccess) e = enqueue_stages(c, q, res, true, 0.0, 0.0, c->run, s);
+    if (e == hipSuccess) e = dg::launch_advance(c->run, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(q, c->qbuf, size_t(c->dm.K) * 5 * c->dm.Np * sizeof(float),
+                         hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "single step");
+  }
+  e = hipMemcpyAsync(&c->host_run, c->run, sizeof(dg::RunScalars), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "dg_run sync");
+  *t_inout = c->host_run.t;
+  if (dt_last) *dt_last = c->host_run.dt;
+  c->last_bad = c->host_run.first_bad;
+  if (c->last_bad >= 0) return fail(c, DG_ENONPHYS, "non-physical state during dg_run");
+  return DG_OK;
+}
+
+int64_t dg_last_step(const dg_ctx* c) { return c ? c->last_bad : -1; }
+
+int dg_prim_to_state(dg_ctx* c, const float* prim, float* q, void* stream) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (!prim || !q) return fail(c, DG_EINVAL, "null argument");
+  hipError_t e = dg::launch_prim_to_state(c->dm, prim, q, false, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DG_OK : hip_fail(c, e, "prim_to_state");
+}
+
+int dg_state_to_prim(dg_ctx* c, const float* q, float* prim, void* stream) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (!prim || !q) return fail(c, DG_EINVAL, "null argument");
+  hipError_t e = dg::launch_prim_to_state(c->dm, q, prim, true, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DG_OK : hip_fail(c, e, "state_to_prim");
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// Launch interface between the C ABI and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "physics.hpp"
+
+namespace dg {
+
+// Everything a stage kernel reads, as device pointers.
+struct DeviceMesh {
+  int N = 0, Np = 0, Nfp = 0;
+  int64_t K = 0;
+  int precision = 0;
+  const float* Aop = nullptr;       // [KT4][MP]   A^T, A = [-Dr -Ds -Dt LIFT]
+  const uint16_t* Abf = nullptr;    // split-BF16 operator (hi, lo) when used
+  const uint8_t* fmask = nullptr;   // [4][Nfp]
+  const uint8_t* nbr_node = nullptr;  // [4][4][6][Nfp]
+  const double* vgeo = nullptr;     // [K][9]   d(r,s,t)/d(x,y,z)
+  const double* sgeo = nullptr;     // [K][4][4] nx ny nz Fscale
+  const int32_t* nbr = nullptr;     // [K][4] neighbour element, or -tag
+  const uint8_t* finfo = nullptr;   // [K][4] neighbour face | orientation << 2
+  Phys phys;
+};
+
+// Device scalars of a run: time, step, CFL reduction and error flags.
+struct RunScalars {
+  double t;
+  double dt;
+  double cfl;
+  double pad0;
+  int64_t step;
+  int64_t first_bad;
+  uint32_t rate_bits;
+  uint32_t bad;
+};
+
+enum StageMode : int { MODE_RHS = 0, MODE_STAGE = 1 };
+
+// One right-hand-side evaluation (MODE_RHS: out = f(q_in)) or one fused
+// low-storage RK stage (MODE_STAGE: res = a res + dt f(q_in);
+// q_out = q_in + b res).  Time is t_host + c dt_host, or read from
+// run->t/run->dt when `run` is not null.
+hipError_t launch_stage(const DeviceMesh& m, int mode, const float* q_in, float* q_out,
+                        float* res, float* out, float a, float b, double c, double t_host,
+                        double dt_host, const RunScalars* run, hipStream_t s);
+
+// Max of (N+1)^2/2 Fscale (|u|+c) over interior face traces into
+// run->rate_bits (as ordered float bits); flags non-physical traces.
+hipError_t launch_rate(const DeviceMesh& m, const float* q, RunScalars* run, hipStream_t s);
+
+// dt = cfl / rate; records the first non-physical step; clears the reduction.
+hipError_t launch_finalize(RunScalars* run, hipStream_t s);
+
+// t += dt; step += 1.
+hipError_t launch_advance(RunScalars* run, hipStream_t s);
+
+hipError_t launch_prim_to_state(const DeviceMesh& m, const float* prim, float* q, bool inverse,
+                                hipStream_t s);
+
+// Raise the dynamic-LDS limit of the stage kernels of order N (call once
+// per process and device before any launch or capture).
+hipError_t prepare_kernels(int N);
+
+// Bytes of dynamic LDS one stage block uses at order N (0 if unsupported).
+size_t stage_lds_bytes(int N);
+
+}  // namespace dg

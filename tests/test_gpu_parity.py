@@ -1,0 +1,173 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances come from FP32 arithmetic: one right-hand side is a sum of
+~3 Np + 4 Nfp products of O(1) operator entries with flux perturbations,
+so its rounding error is a few FP32 ulps (6e-8) times that length relative
+to the flux scale; the bar for one evaluation is 2e-5 relative L2, and the
+bar for 100 steps is the 1e-5 relative L2 of the pressure perturbation that
+the method's FP32 form is specified to meet.
+"""
+import numpy as np
+import pytest
+
+import paper_1710_03887_amd as dg
+from oracle import euler, timestep, norms
+from workloads import (box_kuhn, gaussian_pulse, BC_OUTFLOW_CHAR, BC_WALL, BC_INFLOW,
+                       BC_PASSTHRU)
+from helpers import Pair, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _pulse_state(pair, amp=0.1, width=0.3, center=(0.1, -0.05, 0.02), u=0.0):
+    phys = pair.phys
+    prim = gaussian_pulse(pair.mesh.x, amp * phys.p0, width, center, phys.rho0, phys.p0,
+                          phys.gamma)
+    prim[..., 1] += u * np.sin(np.pi * pair.mesh.x[..., 1])
+    return euler.initial_state(prim, phys.gamma)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
+def test_rhs_parity_box(N):
+    phys = euler.Physics()
+    pair = Pair(box_kuhn(3, jitter=0.05, seed=N), N, phys)
+    q = _pulse_state(pair, u=0.05)
+    r_or = euler.rhs(pair.mesh, q, 0.0, phys)
+    qd = pair.to_device(q)
+    rd = torch.empty_like(qd)
+    dg.dg_rhs(pair.ctx, qd, rd, 0.0)
+    torch.cuda.synchronize()
+    r_gpu = pair.rates_from_device(rd)
+    err = rel_l2(pair.mesh, r_gpu, r_or)
+    print(f"N={N} rhs rel L2 {err:.3e}")
+    assert err < 2e-5
+
+
+@pytest.mark.parametrize("N", [2, 4])
+def test_rhs_parity_all_boundary_kinds(N):
+    """Inflow, wall, pass-through and outflow faces at a time inside the
+    pulse, with a moving ambient state."""
+    phys = euler.Physics(u0=(0.05, -0.02, 0.01), amp=0.1 / 1.4, alpha=10.35)
+    bc = {"x-": BC_INFLOW, "x+": BC_PASSTHRU, "y-": BC_WALL, "y+": BC_WALL,
+          "z-": BC_OUTFLOW_CHAR, "z+": BC_OUTFLOW_CHAR}
+    pair = Pair(box_kuhn((4, 3, 3), jitter=0.05, seed=11, bc=bc), N, phys)
+    q = _pulse_state(pair, amp=0.05, width=0.5)
+    t = 0.13
+    r_or = euler.rhs(pair.mesh, q, t, phys)
+    qd = pair.to_device(q)
+    rd = torch.empty_like(qd)
+    dg.dg_rhs(pair.ctx, qd, rd, t)
+    torch.cuda.synchronize()
+    err = rel_l2(pair.mesh, pair.rates_from_device(rd), r_or)
+    print(f"N={N} mixed-boundary rhs rel L2 {err:.3e}")
+    assert err < 2e-5
+
+
+def test_partial_tile_and_single_element():
+    """K not a multiple of the tile size, down to one element."""
+    phys = euler.Physics()
+    for n in ((1, 1, 1), (2, 1, 1), (3, 2, 1)):
+        pair = Pair(box_kuhn(n, jitter=0.0), 3, phys)
+        q = _pulse_state(pair, width=0.8)
+        r_or = euler.rhs(pair.mesh, q, 0.0, phys)
+        qd = pair.to_device(q)
+        rd = torch.full_like(qd, float("nan"))
+        dg.dg_rhs(pair.ctx, qd, rd, 0.0)
+        torch.cuda.synchronize()
+        err = rel_l2(pair.mesh, pair.rates_from_device(rd), r_or)
+        assert err < 2e-5, (n, err)
+
+
+def test_step_parity():
+    phys = euler.Physics()
+    pair = Pair(box_kuhn(4, jitter=0.05, seed=3), 3, phys)
+    q = _pulse_state(pair)
+    dt = timestep.stable_dt(pair.mesh, q, phys, 0.5)
+    q_or, _ = timestep.lserk_step(lambda y, t: euler.rhs(pair.mesh, y, t, phys), q, 0.0, dt)
+    qd = pair.to_device(q)
+    res = torch.full_like(qd, float("nan"))     # a_1 = 0: contents must be ignored
+    dg.dg_step(pair.ctx, qd, res, 0.0, dt)
+    torch.cuda.synchronize()
+    q_gpu = pair.from_device(qd)
+    err = norms.rel_l2_pressure(pair.mesh, q_gpu, q_or, phys)
+    print(f"one step p' rel L2 {err:.3e}")
+    assert err < 1e-5
+
+
+def test_stable_dt_matches_oracle():
+    phys = euler.Physics()
+    pair = Pair(box_kuhn(6, jitter=0.05), 2, phys)
+    q = _pulse_state(pair, width=0.15)
+    dt_or = timestep.stable_dt(pair.mesh, q, phys, 0.5)
+    dt_gpu = dg.dg_stable_dt(pair.ctx, pair.to_device(q), 0.5)
+    assert abs(dt_gpu / dt_or - 1) < 1e-6
+
+
+def test_run_parity_box_100_steps():
+    """The small workload: box [-1,1]^3 of 6^3 hexes (1296 tets, jitter 5%),
+    N = 2, Gaussian pulse 0.1 p0 / width 0.15, characteristic outflow on
+    every face, CFL 0.5, 100 steps; the GPU takes its own time steps."""
+    phys = euler.Physics()
+    pair = Pair(box_kuhn(6, jitter=0.05, seed=0), 2, phys)
+    q0 = _pulse_state(pair, amp=0.1, width=0.15, center=(0.0, 0.0, 0.0))
+    q_or, t_or, dts = timestep.run(pair.mesh, q0, phys, 100, cfl=0.5)
+    qd = pair.to_device(q0)
+    res = torch.zeros_like(qd)
+    t_gpu, dt_last = dg.dg_run(pair.ctx, qd, res, 100, 0.5, 0.0)
+    assert abs(t_gpu / t_or - 1) < 1e-6
+    assert abs(dt_last / dts[-1] - 1) < 1e-6
+    err = norms.rel_l2_pressure(pair.mesh, pair.from_device(qd), q_or, phys)
+    print(f"100 steps p' rel L2 {err:.3e}  t={t_gpu:.6f}")
+    assert err < 1e-5
+
+
+def test_run_is_deterministic_and_odd_steps():
+    phys = euler.Physics()
+    pair = Pair(box_kuhn(4, jitter=0.05, seed=9), 3, phys)
+    q0 = _pulse_state(pair)
+    outs = []
+    for _ in range(2):
+        qd = pair.to_device(q0)
+        res = torch.zeros_like(qd)
+        dg.dg_run(pair.ctx, qd, res, 7, 0.5, 0.0)
+        outs.append(qd.clone())
+    assert torch.equal(outs[0], outs[1])
+    # 7 steps in one call == 3 + 4 steps in two calls
+    qd = pair.to_device(q0)
+    res = torch.zeros_like(qd)
+    t, _ = dg.dg_run(pair.ctx, qd, res, 3, 0.5, 0.0)
+    dg.dg_run(pair.ctx, qd, res, 4, 0.5, t)
+    assert torch.equal(qd, outs[0])
+
+
+def test_nonphysical_state_is_reported():
+    phys = euler.Physics()
+    pair = Pair(box_kuhn(3), 2, phys)
+    q = _pulse_state(pair)
+    qd = pair.to_device(q)
+    qd[5, 0, :] = -2.0 * phys.rho0        # negative density in element 5
+    res = torch.zeros_like(qd)
+    with pytest.raises(dg.DGError) as e:
+        dg.dg_run(pair.ctx, qd, res, 2, 0.5, 0.0)
+    assert e.value.code == dg.DG_ENONPHYS
+    assert dg.dg_last_step(pair.ctx) == 0
+
+
+def test_prim_state_roundtrip():
+    phys = euler.Physics(u0=(0.1, 0.0, -0.2))
+    pair = Pair(box_kuhn(2), 3, phys)
+    q = _pulse_state(pair, u=0.1)
+    w = euler.primitive(np.transpose(q, (0, 2, 1)), phys.gamma)
+    w0 = np.array([phys.rho0, *phys.u0, phys.p0])
+    prim = np.transpose(w - w0, (0, 2, 1))[:, :, pair.perm]
+    pd = torch.tensor(prim, dtype=torch.float32, device="cuda").contiguous()
+    qd = torch.empty_like(pd)
+    dg.dg_prim_to_state(pair.ctx, pd, qd)
+    back = torch.empty_like(pd)
+    dg.dg_state_to_prim(pair.ctx, qd, back)
+    torch.cuda.synchronize()
+    q_gpu = pair.from_device(qd)
+    assert np.abs(q_gpu - q).max() < 1e-6
+    assert torch.allclose(back, pd, atol=1e-6)
