@@ -1,0 +1,185 @@
+"""Throughput of the nodal DG Euler hot path on one MI355X.
+
+Workload (default): the trumpet in a box -- a bore of radius 0.05 joined to
+an exponential bell of mouth radius 0.4, inside [-0.5, 1.8] x [-1, 1]^2,
+about 200k tetrahedra at order N = 4 (Np = 35), slip walls on the
+instrument, the mouthpiece pulse of 0.1 p0 as inflow, characteristic
+outflow on the box; fluid initially at rest.  One step is one five-stage
+low-storage RK step (five fused stage kernels plus the device-side time-step
+reduction), run through dg_run's captured HIP graph with the state resident
+in HBM.  value = 5 K Np (DOFs) x 5 stages x steps / wall time.
+
+Prints one JSON line.  Also reports, for the dominant kernel (the fused
+stage kernel), its algorithmic HBM bytes per launch over its average
+duration timed with HIP events on the stream it runs on, and the FP64 CPU
+oracle's rate on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+RK4A2, RK4B2 = -567301805773.0 / 1357537059087.0, 5161836677717.0 / 13612068292357.0
+
+
+def stage_bytes(K, Np, reads_res=True):
+    """Algorithmic HBM bytes of one fused stage: state in, residual in/out,
+    state out (FP32), FP64 geometry (9 metric + 4 x (normal, Fscale)) and
+    connectivity (4 int32 neighbours + 4 bytes of face/orientation)."""
+    passes = 4 if reads_res else 3
+    return K * (passes * 5 * Np * 4 + (9 + 16) * 8 + 4 * 4 + 4)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "physics.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1710_03887_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(form, K):
+    """HBM bytes per stage launch from the committed rocprofv3 counter
+    summary, or None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "stage_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(form)
+    except (ValueError, OSError):
+        return None
+    if not rec or rec.get("kernel_hash") != kernel_source_hash() or rec.get("K") != K:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(seconds_budget=30.0):
+    """The FP64 oracle on a bounded sample of the same workload: the same
+    trumpet-in-box geometry at ~20k tetrahedra, N = 4, one LSERK step."""
+    from threadpoolctl import threadpool_info
+    from oracle.operators import RefElement
+    from oracle.mesh import Mesh
+    from oracle import euler, timestep
+    from workloads import trumpet_domain
+    m = trumpet_domain("box", 20_000)
+    ref = RefElement(4)
+    mesh = Mesh(ref, m["xyz"], m["EToV"], m["bc"])
+    phys = euler.Physics(amp=0.1 / 1.4, alpha=2 * np.pi * 565.0 / 343.0)
+    q = np.broadcast_to(phys.q0[None, :, None], (mesh.K, 5, ref.Np)).copy()
+    dt = timestep.stable_dt(mesh, q, phys, 0.5)
+    t0 = time.perf_counter()
+    stages = 0
+    while True:
+        q, _ = timestep.lserk_step(lambda y, t: euler.rhs(mesh, y, t, phys), q, 0.0, dt)
+        stages += 5
+        if time.perf_counter() - t0 > seconds_budget / 3:
+            break
+    el = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    return {"value": 5 * mesh.K * ref.Np * stages / el, "unit": "DOF-stage updates/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": f"trumpet-in-box {mesh.K} tets, N=4, {stages // 5} LSERK step(s) "
+                      f"({stages} RHS evaluations) in {el:.1f} s, FP64 NumPy, "
+                      f"BLAS threads={threads}, host cores={os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--elements", type=int, default=200_000, help="target tetrahedra")
+    ap.add_argument("--order", type=int, default=4)
+    ap.add_argument("--form", choices=("fp32",), default="fp32")
+    ap.add_argument("--kernel-iters", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the element-partitioned multi-GPU path "
+              "(per-stage face-trace exchange) is a design, not part of this build.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1710_03887_amd as dg
+    from workloads import trumpet_domain
+
+    m = trumpet_domain("box", args.elements)
+    N = args.order
+    amp, alpha, p0 = 0.1 / 1.4, 2 * np.pi * 565.0 / 343.0, 1.0 / 1.4
+    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, gamma=1.4, rho0=1.0, p0=p0,
+                           inflow_amp=amp, inflow_alpha=alpha,
+                           precision={"fp32": dg.DG_FP32}[args.form])
+    K, Np = ctx.K, ctx.Np
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    q = torch.zeros((K, 5, Np), dtype=torch.float32, device=dev)   # fluid at rest
+    res = torch.zeros_like(q)
+
+    t, _ = dg.dg_run(ctx, q, res, args.warmup, 0.5, 0.0, stream=stream)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record(stream)
+    t_end, dt_last = dg.dg_run(ctx, q, res, args.steps, 0.5, t, stream=stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = start.elapsed_time(stop)
+    dof = 5 * K * Np
+    value = dof * 5 * args.steps / (ms * 1e-3)
+
+    # dominant kernel: the fused stage, timed alone on the same stream
+    qb = torch.empty_like(q)
+    for _ in range(3):
+        dg.dg_stage(ctx, q, qb, res, RK4A2, RK4B2, t_end, dt_last, stream=stream)
+    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k0.record(stream)
+    for i in range(args.kernel_iters):
+        src, dst = (q, qb) if i % 2 == 0 else (qb, q)
+        dg.dg_stage(ctx, src, dst, res, RK4A2, RK4B2, t_end, dt_last, stream=stream)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    kernel_s = k0.elapsed_time(k1) * 1e-3 / args.kernel_iters
+    nbytes = stage_bytes(K, Np, True)
+    achieved = nbytes / kernel_s / 1e9
+    traffic = measured_traffic(args.form, K)
+
+    out = {
+        "metric": "DOF-stage updates/s",
+        "value": value,
+        "unit": "DOF-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"trumpet-in-box, {K} tets, N={N} (Np={Np}), {args.form} form, "
+                               "inflow pulse 0.1 p0, characteristic outflow, slip walls",
+                   "K": K, "N": N, "Np": Np, "dof": dof, "form": args.form,
+                   "t_end": t_end, "dt_last": dt_last, "wall_s": wall},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "stage_kernel<4,MODE_STAGE>", "kernel_ms": kernel_s * 1e3,
+                     "bytes_per_launch": nbytes},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

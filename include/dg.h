@@ -166,6 +166,18 @@ int dg_rhs(dg_ctx* ctx, const float* q, float* rhs, double t, void* stream);
 int dg_step(dg_ctx* ctx, float* q, float* res, double t, double dt, void* stream);
 
 /*
+ * One fused low-storage RK stage at stage time t_stage:
+ *   res = a res + dt f(q_in, t_stage);  q_out = q_in + b res.
+ * With a == 0 the previous contents of res are not read.  q_in and q_out
+ * must be distinct device buffers (neighbour traces are read from q_in
+ * while q_out is written); all three are FP32 [K][5][Np].  This is the
+ * kernel dg_step and dg_run are made of, exposed for custom integrators
+ * and for timing.  Asynchronous on stream; no allocation.
+ */
+int dg_stage(dg_ctx* ctx, const float* q_in, float* q_out, float* res, double a, double b,
+             double t_stage, double dt, void* stream);
+
+/*
  * nsteps steps with dt = cfl / max over elements, faces and face nodes of
  * (N+1)^2/2 * Fscale * (|u| + c), recomputed on the device at the start of
  * every step from the interior face traces.  The step sequence is captured

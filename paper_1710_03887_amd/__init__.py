@@ -3,9 +3,9 @@
 The compute path is libdg.so (hand-written HIP kernels for gfx950) behind
 the C ABI declared in include/dg.h; this package is its ctypes binding with
 the same function names.  Importing it fails when the library has not been
-built (`python -m paper_1710_03887_amd.build`).
+built (`python paper_1710_03887_amd/build.py`).
 """
 from ._lib import *  # noqa: F401,F403
 from ._lib import (Context, DGError, EXPORTED, dg_mesh_setup, dg_destroy, dg_last_error,  # noqa: F401
                    dg_sizes, dg_nodes, dg_reference_operators, dg_geometry, dg_rhs, dg_step,
-                   dg_run, dg_last_step, dg_stable_dt, dg_prim_to_state, dg_state_to_prim)
+                   dg_run, dg_stage, dg_last_step, dg_stable_dt, dg_prim_to_state, dg_state_to_prim)

@@ -22,7 +22,7 @@ _ERRNAMES = {DG_EINVAL: "DG_EINVAL", DG_EMESH: "DG_EMESH", DG_ENOMEM: "DG_ENOMEM
              DG_EHIP: "DG_EHIP", DG_ENONPHYS: "DG_ENONPHYS", DG_ENODEV: "DG_ENODEV"}
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1710_03887_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing; build it with `python paper_1710_03887_amd/build.py`")
 # torch carries its own HIP runtime under the same soname (libamdhip64.so.7);
 # loading torch first makes libdg.so bind to that one, so that the library
 # and torch's tensors and streams share a single runtime in the process.
@@ -53,6 +53,7 @@ _SIGS = {
     "dg_step": (ctypes.c_int, [_vp, _vp, _vp, _f64, _f64, _vp]),
     "dg_run": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, ctypes.POINTER(_f64),
                               ctypes.POINTER(_f64), _vp]),
+    "dg_stage": (ctypes.c_int, [_vp, _vp, _vp, _vp, _f64, _f64, _f64, _f64, _vp]),
     "dg_last_step": (_i64, [_vp]),
     "dg_stable_dt": (ctypes.c_int, [_vp, _vp, _f64, ctypes.POINTER(_f64), _vp]),
     "dg_prim_to_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -208,6 +209,13 @@ def dg_step(ctx, q, res, t, dt, stream=None):
     _check_state(ctx, res, "res")
     _check(_lib.dg_step(ctx.handle, _ptr(q), _ptr(res), float(t), float(dt), _stream(stream)),
            ctx.handle)
+
+
+def dg_stage(ctx, q_in, q_out, res, a, b, t_stage, dt, stream=None):
+    for x, nm in ((q_in, "q_in"), (q_out, "q_out"), (res, "res")):
+        _check_state(ctx, x, nm)
+    _check(_lib.dg_stage(ctx.handle, _ptr(q_in), _ptr(q_out), _ptr(res), float(a), float(b),
+                         float(t_stage), float(dt), _stream(stream)), ctx.handle)
 
 
 def dg_run(ctx, q, res, nsteps, cfl, t=0.0, stream=None):

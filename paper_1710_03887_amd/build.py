@@ -1,6 +1,6 @@
 """Build libdg.so (HIP, gfx950) in place with hipcc.
 
-    python -m paper_1710_03887_amd.build
+    python paper_1710_03887_amd/build.py
 
 Every HIP source is compiled with packed-FP32 instruction generation
 disabled; the library is written next to this file.

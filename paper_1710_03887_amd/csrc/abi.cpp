@@ -310,6 +310,18 @@ int dg_step(dg_ctx* c, float* q, float* res, double t, double dt, void* stream) 
   return e == hipSuccess ? DG_OK : hip_fail(c, e, "hipMemcpyAsync");
 }
 
+int dg_stage(dg_ctx* c, const float* q_in, float* q_out, float* res, double a, double b,
+             double t_stage, double dt, void* stream) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (!q_in || !q_out || !res) return fail(c, DG_EINVAL, "null state pointer");
+  if (q_in == q_out) return fail(c, DG_EINVAL, "q_in and q_out must differ");
+  hipError_t e = dg::launch_stage(c->dm, dg::MODE_STAGE, q_in, q_out, res, nullptr, float(a),
+                                  float(b), 0.0, t_stage, dt, nullptr,
+                                  static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DG_OK : hip_fail(c, e, "stage launch");
+}
+
 int dg_stable_dt(dg_ctx* c, const float* q, double cfl, double* dt, void* stream) {
   int rc = need_device(c);
   if (rc) return rc;
