@@ -96,20 +96,8 @@ int build_device(dg_ctx* c, hipStream_t s) {
   const auto& mh = c->mesh;
   const int Np = ops.Np, Nfp = ops.Nfp;
   const int64_t K = mh.K;
-  const int KT = 3 * Np + 4 * Nfp, KT4 = (KT + 3) / 4 * 4, MP = (Np + 15) / 16 * 16;
-
-  // contraction operator A = [-Dr -Ds -Dt LIFT], stored transposed and
-  // zero-padded: Aop[k][m] = A[m][k]
-  std::vector<float> Aop(size_t(KT4) * MP, 0.0f);
-  for (int mrow = 0; mrow < Np; ++mrow)
-    for (int k = 0; k < KT; ++k) {
-      double v;
-      if (k < Np) v = -ops.Dr[size_t(mrow) * Np + k];
-      else if (k < 2 * Np) v = -ops.Ds[size_t(mrow) * Np + k - Np];
-      else if (k < 3 * Np) v = -ops.Dt[size_t(mrow) * Np + k - 2 * Np];
-      else v = ops.LIFT[size_t(mrow) * 4 * Nfp + k - 3 * Np];
-      Aop[size_t(k) * MP + mrow] = float(v);
-    }
+  const std::vector<float> Aop =
+      dg::pack_operator(c->dm.N, ops.Dr.data(), ops.Ds.data(), ops.Dt.data(), ops.LIFT.data());
   std::vector<uint8_t> fmask(size_t(4) * Nfp);
   for (size_t i = 0; i < fmask.size(); ++i) fmask[i] = uint8_t(ops.Fmask[i]);
   std::vector<double> sgeo(size_t(K) * 16);
@@ -125,8 +113,13 @@ int build_device(dg_ctx* c, hipStream_t s) {
     finfo[i] = uint8_t(mh.EToF[i] | (mh.orient[i] << 2));
   }
 
-  hipError_t e = dg::prepare_kernels(c->dm.N);
-  if (e != hipSuccess) return hip_fail(c, e, "hipFuncSetAttribute");
+  hipError_t e = dg::prepare_kernels(c->dm.N, &c->dm.blocks_per_cu);
+  if (e != hipSuccess) return hip_fail(c, e, "stage kernel attributes");
+  int dev = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&c->dm.num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(c, e, "device attributes");
   e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(c, e, "hipStreamCreate");
 

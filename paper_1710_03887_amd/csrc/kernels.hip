@@ -1,61 +1,66 @@
 // HIP kernels of the nodal DG Euler hot path (gfx950 / CDNA4).
 //
-// One block owns a tile of E = 16 consecutive elements and does, in LDS:
-//   1. stage the tile's state q' [E][5][Np] (contiguous, coalesced);
-//   2. volume: flux perturbations at every node, contravariant fluxes
-//      Fr = r_x F + r_y G + r_z H (likewise Fs, Ft) written as the first
-//      3 Np rows of the operand B [KT x 5E] (Appendix A, Eq. 10, volume term);
-//   3. surface: interior trace from LDS, exterior trace gathered from the
-//      neighbour element (or a ghost state by tag), local Lax-Friedrichs
-//      jump dF = [n.(F- - F+) - lambda (q- - q+)]/2 scaled by Fscale, as the
-//      last 4 Nfp rows of B (Appendix A, Eq. 10, boundary term);
-//   4. one dense contraction rhs = A B with A = [-Dr -Ds -Dt LIFT]
-//      (Np x KT), on MFMA f32 16x16x4;
-//   5. epilogue: write rhs, or the fused LSERK stage update.
-// Elements are element-major in HBM; blocks are mapped so that each of the
-// 8 XCDs sweeps a contiguous range of tiles (neighbour traces then tend to
-// hit that XCD's L2).
+// Fused stage kernel.  A block of four wavefronts owns a tile of 16
+// consecutive elements at a time (persistent grid; each of the 8 XCDs sweeps
+// a contiguous range of tiles so that neighbour traces mostly hit its L2):
+//   A. the tile's state q' [16][5][Np] and every exterior face trace it needs
+//      are requested at once with asynchronous global->LDS copies (the
+//      neighbour gathers never stall a wavefront one face at a time);
+//   B. the local Lax-Friedrichs speed of each element face,
+//      max over its nodes and both sides of |u.n| + c, is reduced in LDS;
+//   C. the contraction is split over the four wavefronts along its length:
+//      each lane forms the flux of one (node, element) pair -- contravariant
+//      fluxes r_x F + r_y G + r_z H etc. for the volume term, the
+//      Lax-Friedrichs jump [n.(F- - F+) - lambda (q- - q+)] Fscale / 2 for the
+//      surface term (Appendix A, Eq. 10) -- and feeds it straight into the B
+//      operand of MFMA f32 16x16x4 products against A = [-Dr -Ds -Dt | LIFT],
+//      one accumulator set per conserved variable;
+//   D. the four partial sums are added in a fixed order (bitwise
+//      reproducible) and the epilogue writes rhs or the fused low-storage RK
+//      stage update with coalesced accesses.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "kernels.hpp"
 
 namespace dg {
 namespace {
 
-constexpr int kTileE = 16;
-constexpr int kThreads = 256;
+constexpr int kTileE = 16;  // elements per tile (MFMA n = 16)
+constexpr int kWaves = 4;   // wavefronts per block
+constexpr int kThreads = 64 * kWaves;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 template <int N>
 struct Shape {
   static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
   static constexpr int Nfp = (N + 1) * (N + 2) / 2;
   static constexpr int NF = 4 * Nfp;              // face nodes per element
-  static constexpr int KT = 3 * Np + NF;          // contraction length
-  static constexpr int KT4 = (KT + 3) / 4 * 4;    // padded to the MFMA k-step
-  static constexpr int MP = (Np + 15) / 16 * 16;  // rows padded to 16
+  static constexpr int NFQ = NF / 4;              // face-node quads
+  static constexpr int NNQ = (Np + 3) / 4;        // node quads
+  static constexpr int NQP = 4 * NNQ;             // nodes padded to quads
+  static constexpr int KV = 3 * NQP;              // volume contraction rows
+  static constexpr int KT = KV + NF;              // all contraction rows
+  static constexpr int MP = (Np + 15) / 16 * 16;  // output rows padded to 16
   static constexpr int MT = MP / 16;
-  static constexpr int NCOL = 5 * kTileE;         // columns: (element, variable)
-  static constexpr int NT = NCOL / 16;
+  static constexpr int AS = (MP % 32 == 16) ? MP : MP + 16;  // row stride of A
   static constexpr int ST = 5 * Np;               // floats per element state
+  static constexpr bool A_LDS = KT * AS * 4 <= 40 * 1024;
+  static constexpr int tabFloats = (NF + 96 * Nfp + 15) / 16 * 4;
+  static constexpr int scratch = (NF * 5 * kTileE > 1024 * MT) ? NF * 5 * kTileE : 1024 * MT;
   // LDS layout (floats)
-  static constexpr int oB = 0;                    // [KT4][NCOL]
-  static constexpr int oQ = oB + KT4 * NCOL;      // [E][5][Np]
-  static constexpr int oG = oQ + kTileE * ST;     // [E][9] metric
-  static constexpr int oS = oG + kTileE * 9;      // [E][4][4] normal + Fscale
-  static constexpr int oL = oS + kTileE * 16;     // [E][4] face lambda (bits)
+  static constexpr int oA = 0;
+  static constexpr int oTab = oA + (A_LDS ? KT * AS : 0);
+  static constexpr int oQ = oTab + tabFloats;        // [16][5][Np]
+  static constexpr int oP = oQ + kTileE * ST;        // exterior traces / reduction
+  static constexpr int oG = oP + scratch;            // [16][25] metric + faces
+  static constexpr int oL = oG + kTileE * 25;        // [16][4] face speeds
   static constexpr int total = oL + kTileE * 4;
 };
-
-__device__ __forceinline__ int tile_of_block(int b, int G) {
-  // XCD x (= b mod 8) takes a contiguous range of tiles
-  const int x = b & 7, j = b >> 3;
-  const int per = G >> 3, rem = G & 7;
-  return x * per + (x < rem ? x : rem) + j;
-}
 
 __device__ __forceinline__ double stage_time(double c, double t_host, double dt_host,
                                              const RunScalars* run) {
@@ -69,6 +74,10 @@ __device__ __forceinline__ float inflow_pressure(const Phys& P, double t) {
   return 0.0f;
 }
 
+__device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 template <int N, int MODE>
 __global__ __launch_bounds__(kThreads) void stage_kernel(DeviceMesh m, const float* __restrict__ q_in,
                                                          float* __restrict__ q_out,
@@ -77,158 +86,215 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(DeviceMesh m, const flo
                                                          float b_rk, double c_rk, double t_host,
                                                          double dt_host, const RunScalars* run) {
   using S = Shape<N>;
+  constexpr int Np = S::Np, Nfp = S::Nfp, ST = S::ST, MT = S::MT, AS = S::AS, MP = S::MP;
   extern __shared__ float lds[];
-  float* sB = lds + S::oB;
+  const float* sA = S::A_LDS ? lds + S::oA : m.Aop;
+  uint8_t* sFm = reinterpret_cast<uint8_t*>(lds + S::oTab);
+  uint8_t* sNN = sFm + S::NF;
   float* sQ = lds + S::oQ;
+  float* sP = lds + S::oP;
   float* sG = lds + S::oG;
-  float* sS = lds + S::oS;
   unsigned* sL = reinterpret_cast<unsigned*>(lds + S::oL);
   const Phys& P = m.phys;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int e = lane & 15, g = lane >> 4;
 
-  const int G = gridDim.x;
-  const int tile = tile_of_block(blockIdx.x, G);
-  const int64_t e0 = int64_t(tile) * kTileE;
-  const int ne = int(min<int64_t>(kTileE, m.K - e0));
-  const int tid = threadIdx.x;
+  if (S::A_LDS)
+    for (int i = tid; i < S::KT * AS; i += kThreads) lds[S::oA + i] = m.Aop[i];
+  for (int i = tid; i < S::NF; i += kThreads) sFm[i] = m.fmask[i];
+  for (int i = tid; i < 96 * Nfp; i += kThreads) sNN[i] = m.nbr_node[i];
 
-  // 1. stage state and geometry
-  const float* qg = q_in + e0 * S::ST;
-  if (ne == kTileE) {
-    const float4* src = reinterpret_cast<const float4*>(qg);
-    float4* dst = reinterpret_cast<float4*>(sQ);
-    for (int i = tid; i < kTileE * S::ST / 4; i += kThreads) dst[i] = src[i];
-  } else {
-    for (int i = tid; i < kTileE * S::ST; i += kThreads) sQ[i] = (i < ne * S::ST) ? qg[i] : 0.0f;
-  }
-  for (int i = tid; i < kTileE * 9; i += kThreads)
-    sG[i] = (i < ne * 9) ? float(m.vgeo[e0 * 9 + i]) : 0.0f;
-  for (int i = tid; i < kTileE * 16; i += kThreads)
-    sS[i] = (i < ne * 16) ? float(m.sgeo[e0 * 16 + i]) : 0.0f;
-  for (int i = tid; i < kTileE * 4; i += kThreads) sL[i] = 0u;
-  for (int i = S::KT * S::NCOL + tid; i < S::KT4 * S::NCOL; i += kThreads) sB[i] = 0.0f;
-  __syncthreads();
+  const double tst = stage_time(c_rk, t_host, dt_host, run);
+  const float pin = inflow_pressure(P, tst);
+  const float dt = float(run ? run->dt : dt_host);
 
-  // 2. volume fluxes -> rows [a*Np + node] of B
-  for (int it = tid; it < kTileE * S::Np; it += kThreads) {
-    const int e = it / S::Np, i = it - e * S::Np;
-    float q[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) q[v] = sQ[e * S::ST + v * S::Np + i];
-    Prim w;
-    primitive(P, q, w);
-    const float* g = sG + e * 9;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      // contravariant direction: grad of reference coordinate ax
-      const float n[3] = {g[ax * 3 + 0], g[ax * 3 + 1], g[ax * 3 + 2]};
-      float f[5];
-      normal_flux(P, w, n, f);
-      float* row = sB + (ax * S::Np + i) * S::NCOL + e * 5;
-#pragma unroll
-      for (int v = 0; v < 5; ++v) row[v] = (e < ne) ? f[v] : 0.0f;
-    }
-  }
+  const int64_t ntiles = (m.K + kTileE - 1) / kTileE;
+  const int G = gridDim.x, nX = G < 8 ? G : 8;
+  const int x = blockIdx.x % nX, jb = blockIdx.x / nX;
+  const int Gx = G / nX + (x < G % nX ? 1 : 0);
+  const int64_t c0 = ntiles * x / nX, c1 = ntiles * (x + 1) / nX;
 
-  // 3. surface traces; lambda per face via an LDS max
-  constexpr int kFaceIters = (kTileE * S::NF + kThreads - 1) / kThreads;
-  float qm[kFaceIters][5], qp[kFaceIters][5];
-  const float pin = inflow_pressure(P, stage_time(c_rk, t_host, dt_host, run));
-#pragma unroll
-  for (int s = 0; s < kFaceIters; ++s) {
-    const int it = tid + s * kThreads;
-    if (it >= kTileE * S::NF) break;
-    const int e = it / S::NF, fi = it - e * S::NF;
-    const int f = fi / S::Nfp, i = fi - f * S::Nfp;
-    if (e >= ne) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) qm[s][v] = qp[s][v] = 0.0f;
-      continue;
-    }
-    const int node = m.fmask[f * S::Nfp + i];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) qm[s][v] = sQ[e * S::ST + v * S::Np + node];
-    const float* sg = sS + e * 16 + f * 4;
-    const float n[3] = {sg[0], sg[1], sg[2]};
-    Prim wm;
-    primitive(P, qm[s], wm);
-    const int64_t k = e0 + e;
-    const int nb = m.nbr[k * 4 + f];
-    if (nb >= 0) {
-      const int info = m.finfo[k * 4 + f];
-      const int f2 = info & 3, o = info >> 2;
-      const int n2 = m.nbr_node[((f * 4 + f2) * 6 + o) * S::Nfp + i];
-      const float* qn = q_in + int64_t(nb) * S::ST + n2;
-#pragma unroll
-      for (int v = 0; v < 5; ++v) qp[s][v] = qn[v * S::Np];
+  for (int64_t tile = c0 + jb; tile < c1; tile += Gx) {
+    const int64_t k0 = tile * kTileE;
+    const int ne = int(min<int64_t>(kTileE, m.K - k0));
+    const bool valid = e < ne;
+    const int64_t kE = k0 + (valid ? e : 0);
+    __syncthreads();  // previous tile fully consumed (and prologue tables ready)
+
+    // A. asynchronous loads: state tile, exterior traces; geometry
+    const float* qg = q_in + k0 * ST;
+    if (ne == kTileE) {
+      constexpr int n4 = kTileE * ST / 4;
+      for (int j = w; j * 64 < n4; j += kWaves) {
+        const int i4 = j * 64 + lane;
+        if (i4 < n4)
+          __builtin_amdgcn_global_load_lds((void*)(qg + 4 * i4), (lds_ptr_t)(sQ + j * 256), 16, 0, 0);
+      }
     } else {
-      ghost(P, -nb, qm[s], wm, n, pin, qp[s]);
+      for (int i = tid; i < kTileE * ST; i += kThreads) sQ[i] = (i < ne * ST) ? qg[i] : 0.0f;
     }
-    Prim wp;
-    primitive(P, qp[s], wp);
-    const float lam = fmaxf(normal_speed(P, wm, n), normal_speed(P, wp, n));
-    atomicMax(&sL[e * 4 + f], __float_as_uint(lam));
-  }
-  __syncthreads();
+    for (int fq = w; fq < S::NFQ; fq += kWaves) {
+      const int i = 4 * fq + g, f = i / Nfp, ii = i - f * Nfp;
+      const int nb = valid ? m.nbr[kE * 4 + f] : -1;
+      if (nb >= 0) {
+        const int inf = m.finfo[kE * 4 + f];
+        const int n2 = sNN[((f * 4 + (inf & 3)) * 6 + (inf >> 2)) * Nfp + ii];
+        const float* src = q_in + int64_t(nb) * ST + n2;
 #pragma unroll
-  for (int s = 0; s < kFaceIters; ++s) {
-    const int it = tid + s * kThreads;
-    if (it >= kTileE * S::NF) break;
-    const int e = it / S::NF, fi = it - e * S::NF;
-    const int f = fi / S::Nfp;
-    float* row = sB + (3 * S::Np + fi) * S::NCOL + e * 5;
-    if (e >= ne) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) row[v] = 0.0f;
-      continue;
+        for (int v = 0; v < 5; ++v)
+          __builtin_amdgcn_global_load_lds((void*)(src + v * Np), (lds_ptr_t)(sP + (fq * 5 + v) * 64),
+                                           4, 0, 0);
+      }
     }
-    const float* sg = sS + e * 16 + f * 4;
-    const float n[3] = {sg[0], sg[1], sg[2]};
-    const float lam = __uint_as_float(sL[e * 4 + f]);
-    Prim wm, wp;
-    primitive(P, qm[s], wm);
-    primitive(P, qp[s], wp);
-    float fm[5], fp[5];
-    normal_flux(P, wm, n, fm);
-    normal_flux(P, wp, n, fp);
-    const float hs = 0.5f * sg[3];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) row[v] = hs * ((fm[v] - fp[v]) - lam * (qm[s][v] - qp[s][v]));
-  }
-  __syncthreads();
+    for (int i = tid; i < kTileE * 9; i += kThreads) {
+      const int ee = i / 9;
+      sG[ee * 25 + (i - ee * 9)] = (ee < ne) ? float(m.vgeo[k0 * 9 + i]) : 0.0f;
+    }
+    for (int i = tid; i < kTileE * 16; i += kThreads) {
+      const int ee = i >> 4;
+      sG[ee * 25 + 9 + (i & 15)] = (ee < ne) ? float(m.sgeo[k0 * 16 + i]) : 0.0f;
+    }
+    if (tid < kTileE * 4) sL[tid] = 0u;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
 
-  // 4. contraction on MFMA: C[MP x NCOL] = A[MP x KT4] * B[KT4 x NCOL]
-  const int wave = tid >> 6, lane = tid & 63;
-  const int lr = lane & 15, lk = lane >> 4;
-  const double dt = run ? run->dt : dt_host;
-  for (int t = wave; t < S::MT * S::NT; t += kThreads / 64) {
-    const int mt = t % S::MT, nt = t / S::MT;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    const float* Ap = m.Aop + lk * S::MP + mt * 16 + lr;
-    const float* Bp = sB + lk * S::NCOL + nt * 16 + lr;
-#pragma unroll 4
-    for (int ks = 0; ks < S::KT4 / 4; ++ks) {
-      const float av = Ap[ks * 4 * S::MP];
-      const float bv = Bp[ks * 4 * S::NCOL];
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
-    }
-    // 5. epilogue: lane holds rows mt*16 + 4*lk + r of column nt*16 + lr
-    const int col = nt * 16 + lr;
-    const int e = col / 5, v = col - e * 5;
-    if (e < ne) {
-      const int64_t base = (e0 + e) * S::ST + v * S::Np;
+    // residual of this tile, prefetched into registers for the epilogue
+    // (in flight during B and C; barriers only wait for LDS traffic)
+    constexpr int kOut = (kTileE * MP + kThreads - 1) / kThreads;
+    float rpre[5][kOut];
+    if (MODE == MODE_STAGE && a_rk != 0.0f) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int node = mt * 16 + 4 * lk + r;
-        if (node < S::Np) {
-          const int64_t g = base + node;
-          if (MODE == MODE_RHS) {
-            out[g] = acc[r];
-          } else {
-            float rr = float(dt) * acc[r];
-            if (a_rk != 0.0f) rr += a_rk * res[g];
-            res[g] = rr;
-            q_out[g] = sQ[e * S::ST + v * S::Np + node] + b_rk * rr;
-          }
+      for (int i = 0; i < kOut; ++i) {
+        const int o = tid + i * kThreads;
+        const int eo = o / MP, node = o - eo * MP;
+        const bool ok = o < kTileE * MP && node < Np && eo < ne;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) rpre[v][i] = ok ? res[(k0 + eo) * ST + v * Np + node] : 0.0f;
+      }
+    }
+
+    // B. face speeds
+    for (int fq = w; fq < S::NFQ; fq += kWaves) {
+      const int i = 4 * fq + g, f = i / Nfp;
+      const float* gf = sG + e * 25 + 9 + f * 4;
+      const float n[3] = {gf[0], gf[1], gf[2]};
+      const int node = sFm[i];
+      float qm[5], qp[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) qm[v] = sQ[e * ST + v * Np + node];
+      Prim wm;
+      primitive(P, qm, wm);
+      const int nb = valid ? m.nbr[kE * 4 + f] : -BC_PASSTHRU;
+      if (nb >= 0) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qp[v] = sP[(fq * 5 + v) * 64 + lane];
+      } else {
+        ghost(P, -nb, qm, wm, n, pin, qp);
+      }
+      Prim wp;
+      primitive(P, qp, wp);
+      const float lam = fmaxf(normal_speed(P, wm, n), normal_speed(P, wp, n));
+      if (valid) atomicMax(&sL[e * 4 + f], __float_as_uint(lam));
+    }
+    __syncthreads();
+
+    // C. contraction, split over the wavefronts
+    floatx4 acc[5][MT];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[v][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const float* gm = sG + e * 25;
+    for (int nq = w; nq < S::NNQ; nq += kWaves) {
+      const int j = 4 * nq + g;
+      float F[3][5];
+      if (j < Np && valid) {
+        float q[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[v] = sQ[e * ST + v * Np + j];
+        Prim wv;
+        primitive(P, q, wv);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float d[3] = {gm[a * 3 + 0], gm[a * 3 + 1], gm[a * 3 + 2]};
+          normal_flux(P, wv, d, F[a]);
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int v = 0; v < 5; ++v) F[a][v] = 0.0f;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const float av = sA[(a * S::NQP + j) * AS + mt * 16 + e];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) acc[v][mt] = mfma(av, F[a][v], acc[v][mt]);
+        }
+    }
+    for (int fq = (kWaves - 1) - w; fq < S::NFQ; fq += kWaves) {
+      const int i = 4 * fq + g, f = i / Nfp;
+      const float* gf = sG + e * 25 + 9 + f * 4;
+      const float n[3] = {gf[0], gf[1], gf[2]};
+      const int node = sFm[i];
+      float qm[5], qp[5], dF[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) qm[v] = sQ[e * ST + v * Np + node];
+      Prim wm;
+      primitive(P, qm, wm);
+      const int nb = valid ? m.nbr[kE * 4 + f] : -BC_PASSTHRU;
+      if (nb >= 0) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qp[v] = sP[(fq * 5 + v) * 64 + lane];
+      } else {
+        ghost(P, -nb, qm, wm, n, pin, qp);
+      }
+      Prim wp;
+      primitive(P, qp, wp);
+      float fm[5], fp[5];
+      normal_flux(P, wm, n, fm);
+      normal_flux(P, wp, n, fp);
+      const float lam = __uint_as_float(sL[e * 4 + f]);
+      const float hs = valid ? 0.5f * gf[3] : 0.0f;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) dF[v] = hs * ((fm[v] - fp[v]) - lam * (qm[v] - qp[v]));
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const float av = sA[(S::KV + i) * AS + mt * 16 + e];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v][mt] = mfma(av, dF[v], acc[v][mt]);
+      }
+    }
+
+    // D. fixed-order reduction of the four partial sums, then the epilogue
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      __syncthreads();  // sP free (traces consumed / previous round read)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sP[((w * MT + mt) * 4 + r) * 64 + lane] = acc[v][mt][r];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kOut; ++i) {
+        const int o = tid + i * kThreads;
+        const int eo = o / MP, node = o - eo * MP;
+        if (o >= kTileE * MP || node >= Np || eo >= ne) continue;
+        const int mt = node >> 4, gq = (node & 15) >> 2, r = node & 3, l = eo + 16 * gq;
+        float sum = 0.0f;
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ++ww) sum += sP[((ww * MT + mt) * 4 + r) * 64 + l];
+        const int64_t gi = (k0 + eo) * ST + v * Np + node;
+        if (MODE == MODE_RHS) {
+          out[gi] = sum;
+        } else {
+          float rr = dt * sum;
+          if (a_rk != 0.0f) rr += a_rk * rpre[v][i];
+          res[gi] = rr;
+          q_out[gi] = sQ[eo * ST + v * Np + node] + b_rk * rr;
         }
       }
     }
@@ -322,14 +388,21 @@ __global__ void prim_kernel(DeviceMesh m, const float* __restrict__ in, float* _
 }
 
 template <int N>
-hipError_t stage_prepare() {
+hipError_t stage_prepare(int* blocks_per_cu) {
   using S = Shape<N>;
   const int lds = int(S::total * sizeof(float));
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<N, MODE_RHS>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<N, MODE_STAGE>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<N, MODE_STAGE>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  int nb = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&stage_kernel<N, MODE_STAGE>),
+                                                   kThreads, lds);
+  if (e != hipSuccess) return e;
+  *blocks_per_cu = std::max(nb, 1);
+  return hipSuccess;
 }
 
 template <int N>
@@ -337,14 +410,16 @@ hipError_t stage_dispatch(const DeviceMesh& m, int mode, const float* q_in, floa
                           float* res, float* out, float a, float b, double c, double t_host,
                           double dt_host, const RunScalars* run, hipStream_t s) {
   using S = Shape<N>;
-  const int tiles = int((m.K + kTileE - 1) / kTileE);
+  const int64_t tiles = (m.K + kTileE - 1) / kTileE;
+  const int64_t want = (tiles + kWaves - 1) / kWaves;
+  const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(m.num_cu) * m.blocks_per_cu)));
   const size_t lds = size_t(S::total) * sizeof(float);
   if (mode == MODE_RHS)
-    stage_kernel<N, MODE_RHS><<<tiles, kThreads, lds, s>>>(m, q_in, q_out, res, out, a, b, c,
-                                                           t_host, dt_host, run);
+    stage_kernel<N, MODE_RHS><<<blocks, kThreads, lds, s>>>(m, q_in, q_out, res, out, a, b, c,
+                                                            t_host, dt_host, run);
   else
-    stage_kernel<N, MODE_STAGE><<<tiles, kThreads, lds, s>>>(m, q_in, q_out, res, out, a, b, c,
-                                                             t_host, dt_host, run);
+    stage_kernel<N, MODE_STAGE><<<blocks, kThreads, lds, s>>>(m, q_in, q_out, res, out, a, b, c,
+                                                              t_host, dt_host, run);
   return hipGetLastError();
 }
 
@@ -359,6 +434,38 @@ hipError_t rate_dispatch(const DeviceMesh& m, const float* q, RunScalars* run, h
 
 }  // namespace
 
+template <int N>
+std::vector<float> pack_operator_n(const double* Dr, const double* Ds, const double* Dt,
+                                   const double* LIFT) {
+  using S = Shape<N>;
+  std::vector<float> A(size_t(S::KT) * S::AS, 0.0f);
+  const double* D[3] = {Dr, Ds, Dt};
+  for (int k = 0; k < S::KT; ++k)
+    for (int mrow = 0; mrow < S::Np; ++mrow) {
+      double v = 0.0;
+      if (k < S::KV) {
+        const int a = k / S::NQP, j = k - a * S::NQP;
+        if (j < S::Np) v = -D[a][size_t(mrow) * S::Np + j];
+      } else {
+        v = LIFT[size_t(mrow) * S::NF + (k - S::KV)];
+      }
+      A[size_t(k) * S::AS + mrow] = float(v);
+    }
+  return A;
+}
+
+std::vector<float> pack_operator(int N, const double* Dr, const double* Ds, const double* Dt,
+                                 const double* LIFT) {
+  switch (N) {
+    case 1: return pack_operator_n<1>(Dr, Ds, Dt, LIFT);
+    case 2: return pack_operator_n<2>(Dr, Ds, Dt, LIFT);
+    case 3: return pack_operator_n<3>(Dr, Ds, Dt, LIFT);
+    case 4: return pack_operator_n<4>(Dr, Ds, Dt, LIFT);
+    case 5: return pack_operator_n<5>(Dr, Ds, Dt, LIFT);
+    default: return {};
+  }
+}
+
 size_t stage_lds_bytes(int N) {
   switch (N) {
     case 1: return Shape<1>::total * sizeof(float);
@@ -370,13 +477,13 @@ size_t stage_lds_bytes(int N) {
   }
 }
 
-hipError_t prepare_kernels(int N) {
+hipError_t prepare_kernels(int N, int* blocks_per_cu) {
   switch (N) {
-    case 1: return stage_prepare<1>();
-    case 2: return stage_prepare<2>();
-    case 3: return stage_prepare<3>();
-    case 4: return stage_prepare<4>();
-    case 5: return stage_prepare<5>();
+    case 1: return stage_prepare<1>(blocks_per_cu);
+    case 2: return stage_prepare<2>(blocks_per_cu);
+    case 3: return stage_prepare<3>(blocks_per_cu);
+    case 4: return stage_prepare<4>(blocks_per_cu);
+    case 5: return stage_prepare<5>(blocks_per_cu);
     default: return hipErrorInvalidValue;
   }
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "physics.hpp"
 
@@ -14,7 +15,9 @@ struct DeviceMesh {
   int N = 0, Np = 0, Nfp = 0;
   int64_t K = 0;
   int precision = 0;
-  const float* Aop = nullptr;       // [KT4][MP]   A^T, A = [-Dr -Ds -Dt LIFT]
+  int num_cu = 256;          // compute units of the device
+  int blocks_per_cu = 1;     // resident stage blocks per CU
+  const float* Aop = nullptr;       // contraction operator, layout from pack_operator
   const uint16_t* Abf = nullptr;    // split-BF16 operator (hi, lo) when used
   const uint8_t* fmask = nullptr;   // [4][Nfp]
   const uint8_t* nbr_node = nullptr;  // [4][4][6][Nfp]
@@ -62,7 +65,12 @@ hipError_t launch_prim_to_state(const DeviceMesh& m, const float* prim, float* q
 
 // Raise the dynamic-LDS limit of the stage kernels of order N (call once
 // per process and device before any launch or capture).
-hipError_t prepare_kernels(int N);
+hipError_t prepare_kernels(int N, int* blocks_per_cu);
+
+// The contraction operator A = [-Dr -Ds -Dt | LIFT] of order N, transposed
+// and padded in the layout the stage kernel reads (FP32).
+std::vector<float> pack_operator(int N, const double* Dr, const double* Ds, const double* Dt,
+                                 const double* LIFT);
 
 // Bytes of dynamic LDS one stage block uses at order N (0 if unsupported).
 size_t stage_lds_bytes(int N);
