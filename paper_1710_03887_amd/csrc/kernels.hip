@@ -51,14 +51,18 @@ struct Shape {
   static constexpr int ST = 5 * Np;               // floats per element state
   static constexpr bool A_LDS = KT * AS * 4 <= 40 * 1024;
   static constexpr int tabFloats = (NF + 96 * Nfp + 15) / 16 * 4;
-  static constexpr int scratch = (NF * 5 * kTileE > 1024 * MT) ? NF * 5 * kTileE : 1024 * MT;
+  static constexpr int MPS = MP + 4;  // padded row of a partial sum (conflict-free 16-byte writes)
+  static constexpr int scratch = (NF * 5 * kTileE > kWaves * kTileE * MPS) ? NF * 5 * kTileE
+                                                                            : kWaves * kTileE * MPS;
   // LDS layout (floats)
   static constexpr int oA = 0;
   static constexpr int oTab = oA + (A_LDS ? KT * AS : 0);
-  static constexpr int oQ = oTab + tabFloats;        // [16][5][Np]
-  static constexpr int oP = oQ + kTileE * ST;        // exterior traces / reduction
-  static constexpr int oG = oP + scratch;            // [16][25] metric + faces
-  static constexpr int oL = oG + kTileE * 25;        // [16][4] face speeds
+  static constexpr int oQ = oTab + tabFloats;        // [16][5][Np] state tile
+  static constexpr int oR = oQ + kTileE * ST;        // [16][5][Np] residual tile
+  static constexpr int oP = oR + kTileE * ST;        // exterior traces / reduction
+  static constexpr int oG = oP + scratch;            // FP64 [16][9] metric, [16][16] faces
+  static constexpr int oF = oG + kTileE * 25 * 2;    // FP32 [16][17] faces, [16][9] metric
+  static constexpr int oL = oF + kTileE * 26;        // [16][4] face speeds
   static constexpr int total = oL + kTileE * 4;
 };
 
@@ -74,12 +78,19 @@ __device__ __forceinline__ float inflow_pressure(const Phys& P, double t) {
   return 0.0f;
 }
 
+// x[f] for a runtime face index f in 0..3 held in registers (selects, no
+// dynamic register indexing)
+template <class T>
+__device__ __forceinline__ T pick4(const T* x, int f) {
+  return f == 0 ? x[0] : f == 1 ? x[1] : f == 2 ? x[2] : x[3];
+}
+
 __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int N, int MODE>
-__global__ __launch_bounds__(kThreads) void stage_kernel(DeviceMesh m, const float* __restrict__ q_in,
+template <int N, int MODE, bool MOVING>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel(DeviceMesh m, const float* __restrict__ q_in,
                                                          float* __restrict__ q_out,
                                                          float* __restrict__ res,
                                                          float* __restrict__ out, float a_rk,
@@ -92,8 +103,12 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(DeviceMesh m, const flo
   uint8_t* sFm = reinterpret_cast<uint8_t*>(lds + S::oTab);
   uint8_t* sNN = sFm + S::NF;
   float* sQ = lds + S::oQ;
+  float* sR = lds + S::oR;
   float* sP = lds + S::oP;
-  float* sG = lds + S::oG;
+  const double* sVg = reinterpret_cast<const double*>(lds + S::oG);   // [16][9]
+  const double* sSg = sVg + kTileE * 9;                               // [16][16]
+  float* sFg = lds + S::oF;             // [16][17]: n, Fscale per face (row padded)
+  float* sMg = sFg + kTileE * 17;       // [16][9]: metric
   unsigned* sL = reinterpret_cast<unsigned*>(lds + S::oL);
   const Phys& P = m.phys;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -114,87 +129,151 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(DeviceMesh m, const flo
   const int Gx = G / nX + (x < G % nX ? 1 : 0);
   const int64_t c0 = ntiles * x / nX, c1 = ntiles * (x + 1) / nX;
 
+  // connectivity of a lane's element, one tile ahead: 4 neighbours + packed
+  // (neighbour face | orientation << 2) bytes
+  auto load_conn = [&](int64_t t, int4& nb4, unsigned& fi4) {
+    const int64_t kk = t * kTileE + e;
+    if (t < c1 && kk < m.K) {
+      nb4 = reinterpret_cast<const int4*>(m.nbr)[kk];
+      fi4 = reinterpret_cast<const unsigned*>(m.finfo)[kk];
+    } else {
+      nb4 = make_int4(-BC_PASSTHRU, -BC_PASSTHRU, -BC_PASSTHRU, -BC_PASSTHRU);
+      fi4 = 0u;
+    }
+  };
+  int4 nbN;
+  unsigned fiN;
+  load_conn(c0 + jb, nbN, fiN);
+  constexpr int kOut = (kTileE * MP + kThreads - 1) / kThreads;
+  constexpr int kFQ = (S::NFQ + kWaves - 1) / kWaves;
+
+  // exterior-trace offsets (neighbour element * ST + node) of this lane's
+  // face quads, or -1 on boundary faces; computed one tile ahead so that the
+  // gathers are issued without an LDS table read in front of them
+  int goff[kFQ];
+  auto gather_offsets = [&](int64_t t) {
+    const bool ok = t < c1 && t * kTileE + e < m.K;
+    const int nbv[4] = {nbN.x, nbN.y, nbN.z, nbN.w};
+#pragma unroll
+    for (int kq = 0; kq < kFQ; ++kq) {
+      const int fq = w + kWaves * kq;
+      const int i = 4 * fq + g, f = i / Nfp, ii = i - f * Nfp;
+      const int nb = pick4(nbv, f);
+      int off = -1;
+      if (ok && fq < S::NFQ && nb >= 0) {
+        const int inf = (fiN >> (8 * f)) & 0xff;
+        off = nb * ST + sNN[((f * 4 + (inf & 3)) * 6 + (inf >> 2)) * Nfp + ii];
+      }
+      goff[kq] = off;
+    }
+  };
+  __syncthreads();  // tables in LDS
+  gather_offsets(c0 + jb);
+
   for (int64_t tile = c0 + jb; tile < c1; tile += Gx) {
     const int64_t k0 = tile * kTileE;
     const int ne = int(min<int64_t>(kTileE, m.K - k0));
     const bool valid = e < ne;
-    const int64_t kE = k0 + (valid ? e : 0);
+    const int nbr[4] = {nbN.x, nbN.y, nbN.z, nbN.w};
     __syncthreads();  // previous tile fully consumed (and prologue tables ready)
 
-    // A. asynchronous loads: state tile, exterior traces; geometry
-    const float* qg = q_in + k0 * ST;
-    if (ne == kTileE) {
-      constexpr int n4 = kTileE * ST / 4;
-      for (int j = w; j * 64 < n4; j += kWaves) {
-        const int i4 = j * 64 + lane;
-        if (i4 < n4)
-          __builtin_amdgcn_global_load_lds((void*)(qg + 4 * i4), (lds_ptr_t)(sQ + j * 256), 16, 0, 0);
-      }
-    } else {
-      for (int i = tid; i < kTileE * ST; i += kThreads) sQ[i] = (i < ne * ST) ? qg[i] : 0.0f;
-    }
-    for (int fq = w; fq < S::NFQ; fq += kWaves) {
-      const int i = 4 * fq + g, f = i / Nfp, ii = i - f * Nfp;
-      const int nb = valid ? m.nbr[kE * 4 + f] : -1;
-      if (nb >= 0) {
-        const int inf = m.finfo[kE * 4 + f];
-        const int n2 = sNN[((f * 4 + (inf & 3)) * 6 + (inf >> 2)) * Nfp + ii];
-        const float* src = q_in + int64_t(nb) * ST + n2;
+    // A. asynchronous loads: exterior traces (offsets precomputed), then the
+    // state and residual tiles and the FP64 geometry
+    if (tid < kTileE * 4) sL[tid] = 0u;
+#pragma unroll
+    for (int kq = 0; kq < kFQ; ++kq) {
+      const int fq = w + kWaves * kq;
+      if (goff[kq] >= 0) {
+        const float* src = q_in + goff[kq];
 #pragma unroll
         for (int v = 0; v < 5; ++v)
           __builtin_amdgcn_global_load_lds((void*)(src + v * Np), (lds_ptr_t)(sP + (fq * 5 + v) * 64),
                                            4, 0, 0);
       }
     }
-    for (int i = tid; i < kTileE * 9; i += kThreads) {
-      const int ee = i / 9;
-      sG[ee * 25 + (i - ee * 9)] = (ee < ne) ? float(m.vgeo[k0 * 9 + i]) : 0.0f;
+    // state and residual tiles, FP64 geometry
+    const float* qg = q_in + k0 * ST;
+    const bool want_res = MODE == MODE_STAGE && a_rk != 0.0f;
+    if (ne == kTileE) {
+      constexpr int n4 = kTileE * ST / 4;
+      for (int j = w; j * 64 < n4; j += kWaves) {
+        const int i4 = j * 64 + lane;
+        if (i4 < n4) {
+          __builtin_amdgcn_global_load_lds((void*)(qg + 4 * i4), (lds_ptr_t)(sQ + j * 256), 16, 0, 0);
+          if (want_res)
+            __builtin_amdgcn_global_load_lds((void*)(res + k0 * ST + 4 * i4),
+                                             (lds_ptr_t)(sR + j * 256), 16, 0, 0);
+        }
+      }
+      // FP64 geometry of the tile: 1152 + 2048 contiguous bytes, 16-byte chunks
+      if (w == kWaves - 1) {
+        const char* vsrc = reinterpret_cast<const char*>(m.vgeo + k0 * 9);
+        const char* ssrc = reinterpret_cast<const char*>(m.sgeo + k0 * 16);
+        char* gdst = reinterpret_cast<char*>(lds + S::oG);
+        __builtin_amdgcn_global_load_lds((void*)(vsrc + 16 * lane), (lds_ptr_t)(gdst), 16, 0, 0);
+        if (lane < 8)
+          __builtin_amdgcn_global_load_lds((void*)(vsrc + 1024 + 16 * lane), (lds_ptr_t)(gdst + 1024),
+                                           16, 0, 0);
+        __builtin_amdgcn_global_load_lds((void*)(ssrc + 16 * lane), (lds_ptr_t)(gdst + 1152), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((void*)(ssrc + 1024 + 16 * lane), (lds_ptr_t)(gdst + 2176),
+                                         16, 0, 0);
+      }
+    } else {
+      for (int i = tid; i < kTileE * ST; i += kThreads) {
+        sQ[i] = (i < ne * ST) ? qg[i] : 0.0f;
+        if (want_res) sR[i] = (i < ne * ST) ? res[k0 * ST + i] : 0.0f;
+      }
+      double* gd = reinterpret_cast<double*>(lds + S::oG);
+      for (int i = tid; i < kTileE * 9; i += kThreads) gd[i] = (i < ne * 9) ? m.vgeo[k0 * 9 + i] : 0.0;
+      for (int i = tid; i < kTileE * 16; i += kThreads)
+        gd[kTileE * 9 + i] = (i < ne * 16) ? m.sgeo[k0 * 16 + i] : 0.0;
     }
-    for (int i = tid; i < kTileE * 16; i += kThreads) {
-      const int ee = i >> 4;
-      sG[ee * 25 + 9 + (i & 15)] = (ee < ne) ? float(m.sgeo[k0 * 16 + i]) : 0.0f;
-    }
-    if (tid < kTileE * 4) sL[tid] = 0u;
+    load_conn(tile + Gx, nbN, fiN);  // next tile's connectivity, in flight meanwhile
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    // geometry to FP32 with padded rows (avoids 16-way bank conflicts)
+    if (tid < kTileE * 16) sFg[(tid >> 4) * 17 + (tid & 15)] = float(sSg[tid]);
+    if (tid < kTileE * 9) sMg[tid] = float(sVg[tid]);
+    gather_offsets(tile + Gx);
+    __syncthreads();
 
-    // residual of this tile, prefetched into registers for the epilogue
-    // (in flight during B and C; barriers only wait for LDS traffic)
-    constexpr int kOut = (kTileE * MP + kThreads - 1) / kThreads;
-    float rpre[5][kOut];
-    if (MODE == MODE_STAGE && a_rk != 0.0f) {
+    // B. surface: traces, face speeds and the normal-flux difference
+    //    n.(F- - F+) (stored over the staged exterior trace); q- - q+ stays
+    //    in registers for the contraction pass (same lanes, same quads)
+    float dq[kFQ][5];
 #pragma unroll
-      for (int i = 0; i < kOut; ++i) {
-        const int o = tid + i * kThreads;
-        const int eo = o / MP, node = o - eo * MP;
-        const bool ok = o < kTileE * MP && node < Np && eo < ne;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) rpre[v][i] = ok ? res[(k0 + eo) * ST + v * Np + node] : 0.0f;
-      }
-    }
-
-    // B. face speeds
-    for (int fq = w; fq < S::NFQ; fq += kWaves) {
+    for (int kq = 0; kq < kFQ; ++kq) {
+      const int fq = w + kWaves * kq;
+      if (fq >= S::NFQ) break;
       const int i = 4 * fq + g, f = i / Nfp;
-      const float* gf = sG + e * 25 + 9 + f * 4;
+      const float* gf = sFg + e * 17 + f * 4;
       const float n[3] = {gf[0], gf[1], gf[2]};
       const int node = sFm[i];
       float qm[5], qp[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) qm[v] = sQ[e * ST + v * Np + node];
       Prim wm;
-      primitive(P, qm, wm);
-      const int nb = valid ? m.nbr[kE * 4 + f] : -BC_PASSTHRU;
+      primitive<MOVING>(P, qm, wm);
+      const int nb = valid ? pick4(nbr, f) : -BC_PASSTHRU;
+      float* slot = sP + fq * 5 * 64 + lane;
       if (nb >= 0) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qp[v] = sP[(fq * 5 + v) * 64 + lane];
+        for (int v = 0; v < 5; ++v) qp[v] = slot[v * 64];
       } else {
         ghost(P, -nb, qm, wm, n, pin, qp);
       }
       Prim wp;
-      primitive(P, qp, wp);
-      const float lam = fmaxf(normal_speed(P, wm, n), normal_speed(P, wp, n));
+      primitive<MOVING>(P, qp, wp);
+      const float lam = fmaxf(normal_speed<MOVING>(P, wm, n), normal_speed<MOVING>(P, wp, n));
       if (valid) atomicMax(&sL[e * 4 + f], __float_as_uint(lam));
+      float fm[5], fp[5];
+      normal_flux<MOVING>(P, wm, n, fm);
+      normal_flux<MOVING>(P, wp, n, fp);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        slot[v * 64] = fm[v] - fp[v];
+        dq[kq][v] = qm[v] - qp[v];
+      }
     }
     __syncthreads();
 
@@ -205,8 +284,10 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(DeviceMesh m, const flo
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) acc[v][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    const float* gm = sG + e * 25;
-    for (int nq = w; nq < S::NNQ; nq += kWaves) {
+    float gm[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) gm[i] = sMg[e * 9 + i];
+    for (int nq = (w + 1) % kWaves; nq < S::NNQ; nq += kWaves) {
       const int j = 4 * nq + g;
       float F[3][5];
       if (j < Np && valid) {
@@ -214,11 +295,11 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(DeviceMesh m, const flo
 #pragma unroll
         for (int v = 0; v < 5; ++v) q[v] = sQ[e * ST + v * Np + j];
         Prim wv;
-        primitive(P, q, wv);
+        primitive<MOVING>(P, q, wv);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const float d[3] = {gm[a * 3 + 0], gm[a * 3 + 1], gm[a * 3 + 2]};
-          normal_flux(P, wv, d, F[a]);
+          normal_flux<MOVING>(P, wv, d, F[a]);
         }
       } else {
 #pragma unroll
@@ -235,32 +316,18 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(DeviceMesh m, const flo
           for (int v = 0; v < 5; ++v) acc[v][mt] = mfma(av, F[a][v], acc[v][mt]);
         }
     }
-    for (int fq = (kWaves - 1) - w; fq < S::NFQ; fq += kWaves) {
+    // surface term: dF = Fscale/2 [n.(F- - F+) - lambda (q- - q+)]
+#pragma unroll
+    for (int kq = 0; kq < kFQ; ++kq) {
+      const int fq = w + kWaves * kq;
+      if (fq >= S::NFQ) break;
       const int i = 4 * fq + g, f = i / Nfp;
-      const float* gf = sG + e * 25 + 9 + f * 4;
-      const float n[3] = {gf[0], gf[1], gf[2]};
-      const int node = sFm[i];
-      float qm[5], qp[5], dF[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) qm[v] = sQ[e * ST + v * Np + node];
-      Prim wm;
-      primitive(P, qm, wm);
-      const int nb = valid ? m.nbr[kE * 4 + f] : -BC_PASSTHRU;
-      if (nb >= 0) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) qp[v] = sP[(fq * 5 + v) * 64 + lane];
-      } else {
-        ghost(P, -nb, qm, wm, n, pin, qp);
-      }
-      Prim wp;
-      primitive(P, qp, wp);
-      float fm[5], fp[5];
-      normal_flux(P, wm, n, fm);
-      normal_flux(P, wp, n, fp);
       const float lam = __uint_as_float(sL[e * 4 + f]);
-      const float hs = valid ? 0.5f * gf[3] : 0.0f;
+      const float hs = valid ? 0.5f * sFg[e * 17 + f * 4 + 3] : 0.0f;
+      const float* slot = sP + fq * 5 * 64 + lane;
+      float dF[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) dF[v] = hs * ((fm[v] - fp[v]) - lam * (qm[v] - qp[v]));
+      for (int v = 0; v < 5; ++v) dF[v] = hs * (slot[v * 64] - lam * dq[kq][v]);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const float av = sA[(S::KV + i) * AS + mt * 16 + e];
@@ -273,28 +340,38 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(DeviceMesh m, const flo
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       __syncthreads();  // sP free (traces consumed / previous round read)
+      // partial sums transposed to [wave][element][node]: lane (g, e) holds
+      // nodes mt*16 + 4g .. +3 of element e
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sP[((w * MT + mt) * 4 + r) * 64 + lane] = acc[v][mt][r];
+        *reinterpret_cast<floatx4*>(sP + (w * kTileE + e) * S::MPS + mt * 16 + 4 * g) = acc[v][mt];
       __syncthreads();
+      float sum[kOut], qv[kOut], rv[kOut];
+      int64_t gidx[kOut];
+      bool okv[kOut];
 #pragma unroll
       for (int i = 0; i < kOut; ++i) {
-        const int o = tid + i * kThreads;
+        const int o = min(tid + i * kThreads, kTileE * MP - 1);
         const int eo = o / MP, node = o - eo * MP;
-        if (o >= kTileE * MP || node >= Np || eo >= ne) continue;
-        const int mt = node >> 4, gq = (node & 15) >> 2, r = node & 3, l = eo + 16 * gq;
-        float sum = 0.0f;
+        okv[i] = (tid + i * kThreads < kTileE * MP) && node < Np && eo < ne;
+        const int nd = node < Np ? node : Np - 1;
+        float acc_s = 0.0f;
 #pragma unroll
-        for (int ww = 0; ww < kWaves; ++ww) sum += sP[((ww * MT + mt) * 4 + r) * 64 + l];
-        const int64_t gi = (k0 + eo) * ST + v * Np + node;
+        for (int ww = 0; ww < kWaves; ++ww) acc_s += sP[(ww * kTileE + eo) * S::MPS + node];
+        sum[i] = acc_s;
+        qv[i] = sQ[eo * ST + v * Np + nd];
+        rv[i] = (MODE == MODE_STAGE && a_rk != 0.0f) ? sR[eo * ST + v * Np + nd] : 0.0f;
+        gidx[i] = (k0 + eo) * ST + v * Np + nd;
+      }
+#pragma unroll
+      for (int i = 0; i < kOut; ++i) {
+        if (!okv[i]) continue;
         if (MODE == MODE_RHS) {
-          out[gi] = sum;
+          out[gidx[i]] = sum[i];
         } else {
-          float rr = dt * sum;
-          if (a_rk != 0.0f) rr += a_rk * rpre[v][i];
-          res[gi] = rr;
-          q_out[gi] = sQ[eo * ST + v * Np + node] + b_rk * rr;
+          const float rr = dt * sum[i] + a_rk * rv[i];
+          res[gidx[i]] = rr;
+          q_out[gidx[i]] = qv[i] + b_rk * rr;
         }
       }
     }
@@ -387,22 +464,35 @@ __global__ void prim_kernel(DeviceMesh m, const float* __restrict__ in, float* _
   }
 }
 
+template <int N, int MODE, bool MOVING>
+hipError_t set_lds_limit(int lds) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<N, MODE, MOVING>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
 template <int N>
 hipError_t stage_prepare(int* blocks_per_cu) {
   using S = Shape<N>;
   const int lds = int(S::total * sizeof(float));
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<N, MODE_RHS>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<N, MODE_STAGE>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipError_t e = set_lds_limit<N, MODE_RHS, false>(lds);
+  if (e == hipSuccess) e = set_lds_limit<N, MODE_STAGE, false>(lds);
+  if (e == hipSuccess) e = set_lds_limit<N, MODE_RHS, true>(lds);
+  if (e == hipSuccess) e = set_lds_limit<N, MODE_STAGE, true>(lds);
   if (e != hipSuccess) return e;
   int nb = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&stage_kernel<N, MODE_STAGE>),
-                                                   kThreads, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &nb, reinterpret_cast<const void*>(&stage_kernel<N, MODE_STAGE, true>), kThreads, lds);
   if (e != hipSuccess) return e;
   *blocks_per_cu = std::max(nb, 1);
   return hipSuccess;
+}
+
+template <int N, int MODE, bool MOVING>
+void stage_launch(int blocks, size_t lds, hipStream_t s, const DeviceMesh& m, const float* q_in,
+                  float* q_out, float* res, float* out, float a, float b, double c,
+                  double t_host, double dt_host, const RunScalars* run) {
+  stage_kernel<N, MODE, MOVING><<<blocks, kThreads, lds, s>>>(m, q_in, q_out, res, out, a, b, c,
+                                                              t_host, dt_host, run);
 }
 
 template <int N>
@@ -411,15 +501,16 @@ hipError_t stage_dispatch(const DeviceMesh& m, int mode, const float* q_in, floa
                           double dt_host, const RunScalars* run, hipStream_t s) {
   using S = Shape<N>;
   const int64_t tiles = (m.K + kTileE - 1) / kTileE;
-  const int64_t want = (tiles + kWaves - 1) / kWaves;
-  const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(m.num_cu) * m.blocks_per_cu)));
+  const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(tiles, int64_t(m.num_cu) * m.blocks_per_cu)));
   const size_t lds = size_t(S::total) * sizeof(float);
-  if (mode == MODE_RHS)
-    stage_kernel<N, MODE_RHS><<<blocks, kThreads, lds, s>>>(m, q_in, q_out, res, out, a, b, c,
-                                                            t_host, dt_host, run);
-  else
-    stage_kernel<N, MODE_STAGE><<<blocks, kThreads, lds, s>>>(m, q_in, q_out, res, out, a, b, c,
-                                                              t_host, dt_host, run);
+  const bool moving = m.phys.u0[0] != 0.0f || m.phys.u0[1] != 0.0f || m.phys.u0[2] != 0.0f;
+  if (mode == MODE_RHS) {
+    if (moving) stage_launch<N, MODE_RHS, true>(blocks, lds, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+    else stage_launch<N, MODE_RHS, false>(blocks, lds, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+  } else {
+    if (moving) stage_launch<N, MODE_STAGE, true>(blocks, lds, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+    else stage_launch<N, MODE_STAGE, false>(blocks, lds, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+  }
   return hipGetLastError();
 }
 

@@ -32,7 +32,28 @@ struct Prim {
   float E, Ep;       // E, E'
 };
 
+// MOVING = false specializes everything below to an ambient state at rest
+// (u0 = 0), where the ambient-velocity terms vanish identically.
+template <bool MOVING = true>
 __device__ __forceinline__ void primitive(const Phys& P, const float q[5], Prim& w) {
+  if (!MOVING) {
+    w.rhop = q[0];
+    w.rho = P.rho0 + q[0];
+    const float ir = 1.0f / w.rho;
+    float kin = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      w.mp[d] = q[1 + d];
+      w.m[d] = q[1 + d];
+      w.du[d] = q[1 + d] * ir;
+      kin += w.mp[d] * w.du[d];
+    }
+    w.Ep = q[4];
+    w.E = P.E0 + q[4];
+    w.pp = P.gm1 * (q[4] - 0.5f * kin);
+    w.p = P.p0 + w.pp;
+    return;
+  }
   w.rhop = q[0];
   w.rho = P.rho0 + q[0];
   const float ir = 1.0f / w.rho;
@@ -51,8 +72,17 @@ __device__ __forceinline__ void primitive(const Phys& P, const float q[5], Prim&
 }
 
 // Flux perturbation along a unit (or any) direction n: n.F(q) - n.F(q0).
+template <bool MOVING = true>
 __device__ __forceinline__ void normal_flux(const Phys& P, const Prim& w, const float n[3],
                                             float f[5]) {
+  if (!MOVING) {
+    const float dun = w.du[0] * n[0] + w.du[1] * n[1] + w.du[2] * n[2];
+    f[0] = w.mp[0] * n[0] + w.mp[1] * n[1] + w.mp[2] * n[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[1 + i] = w.mp[i] * dun + n[i] * w.pp;
+    f[4] = dun * (w.E + w.p);
+    return;
+  }
   const float dun = w.du[0] * n[0] + w.du[1] * n[1] + w.du[2] * n[2];
   const float u0n = P.u0[0] * n[0] + P.u0[1] * n[1] + P.u0[2] * n[2];
   f[0] = w.mp[0] * n[0] + w.mp[1] * n[1] + w.mp[2] * n[2];
@@ -62,7 +92,10 @@ __device__ __forceinline__ void normal_flux(const Phys& P, const Prim& w, const 
 }
 
 // |u.n| + c
+template <bool MOVING = true>
 __device__ __forceinline__ float normal_speed(const Phys& P, const Prim& w, const float n[3]) {
+  if (!MOVING)
+    return fabsf(w.du[0] * n[0] + w.du[1] * n[1] + w.du[2] * n[2]) + sqrtf(P.gamma * w.p / w.rho);
   const float un = (P.u0[0] + w.du[0]) * n[0] + (P.u0[1] + w.du[1]) * n[1] +
                    (P.u0[2] + w.du[2]) * n[2];
   return fabsf(un) + sqrtf(P.gamma * w.p / w.rho);
