@@ -98,7 +98,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--elements", type=int, default=200_000, help="target tetrahedra")
     ap.add_argument("--order", type=int, default=4)
-    ap.add_argument("--form", choices=("fp32",), default="fp32")
+    ap.add_argument("--form", choices=("fp32", "bf16"), default="fp32")
     ap.add_argument("--kernel-iters", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -117,7 +117,7 @@ def main():
     amp, alpha, p0 = 0.1 / 1.4, 2 * np.pi * 565.0 / 343.0, 1.0 / 1.4
     ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, gamma=1.4, rho0=1.0, p0=p0,
                            inflow_amp=amp, inflow_alpha=alpha,
-                           precision={"fp32": dg.DG_FP32}[args.form])
+                           precision={"fp32": dg.DG_FP32, "bf16": dg.DG_SPLIT_BF16}[args.form])
     K, Np = ctx.K, ctx.Np
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)

@@ -113,7 +113,7 @@ int build_device(dg_ctx* c, hipStream_t s) {
     finfo[i] = uint8_t(mh.EToF[i] | (mh.orient[i] << 2));
   }
 
-  hipError_t e = dg::prepare_kernels(c->dm.N, &c->dm.blocks_per_cu);
+  hipError_t e = dg::prepare_kernels(c->dm.N, c->dm.precision, &c->dm.blocks_per_cu);
   if (e != hipSuccess) return hip_fail(c, e, "stage kernel attributes");
   int dev = 0;
   e = hipGetDevice(&dev);
@@ -129,6 +129,13 @@ int build_device(dg_ctx* c, hipStream_t s) {
   int32_t* dN;
   int rc;
   if ((rc = upload(c, Aop.data(), Aop.size(), &dA, s))) return rc;
+  if (c->dm.precision == DG_SPLIT_BF16) {
+    const std::vector<uint16_t> Abf =
+        dg::pack_operator_bf16(c->dm.N, ops.Dr.data(), ops.Ds.data(), ops.Dt.data());
+    uint16_t* dAb;
+    if ((rc = upload(c, Abf.data(), Abf.size(), &dAb, s))) return rc;
+    c->dm.Abf = dAb;
+  }
   if ((rc = upload(c, fmask.data(), fmask.size(), &dF, s))) return rc;
   if ((rc = upload(c, ops.nbr_node.data(), ops.nbr_node.size(), &dNN, s))) return rc;
   if ((rc = upload(c, mh.drst_dx.data(), mh.drst_dx.size(), &dV, s))) return rc;

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "kernels.hpp"
@@ -33,9 +34,12 @@ constexpr int kWaves = 4;   // wavefronts per block
 constexpr int kThreads = 64 * kWaves;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
-template <int N>
+enum : int { PREC_FP32 = 0, PREC_BF16 = 1 };
+
+template <int N, int PREC = PREC_FP32>
 struct Shape {
   static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
   static constexpr int Nfp = (N + 1) * (N + 2) / 2;
@@ -49,21 +53,31 @@ struct Shape {
   static constexpr int MT = MP / 16;
   static constexpr int AS = (MP % 32 == 16) ? MP : MP + 16;  // row stride of A
   static constexpr int ST = 5 * Np;               // floats per element state
-  static constexpr bool A_LDS = KT * AS * 4 <= 40 * 1024;
+  // split-BF16 volume: k-blocks of 32 = 4 lane groups x (2 nodes x 3
+  // directions + 2 zero pads); the operator halves hi, lo are [MP][KVB]
+  static constexpr int NKB = (Np + 7) / 8;
+  static constexpr int KVB = 32 * NKB;
+  // rows of the FP32 operator kept in LDS: all, or the LIFT rows only
+  static constexpr int AROW0 = (PREC == PREC_BF16) ? KV : 0;
+  static constexpr bool A_LDS = (KT - AROW0) * AS * 4 <= 40 * 1024;
   static constexpr int tabFloats = (NF + 96 * Nfp + 15) / 16 * 4;
   static constexpr int MPS = MP + 4;  // padded row of a partial sum (conflict-free 16-byte writes)
   static constexpr int scratch = (NF * 5 * kTileE > kWaves * kTileE * MPS) ? NF * 5 * kTileE
                                                                             : kWaves * kTileE * MPS;
   // LDS layout (floats)
   static constexpr int oA = 0;
-  static constexpr int oTab = oA + (A_LDS ? KT * AS : 0);
+  static constexpr int oTab = oA + (A_LDS ? (KT - AROW0) * AS : 0);
   static constexpr int oQ = oTab + tabFloats;        // [16][5][Np] state tile
   static constexpr int oR = oQ + kTileE * ST;        // [16][5][Np] residual tile
   static constexpr int oP = oR + kTileE * ST;        // exterior traces / reduction
   static constexpr int oG = oP + scratch;            // FP64 [16][9] metric, [16][16] faces
   static constexpr int oF = oG + kTileE * 25 * 2;    // FP32 [16][17] faces, [16][9] metric
   static constexpr int oL = oF + kTileE * 26;        // [16][4] face speeds
-  static constexpr int total = oL + kTileE * 4;
+  // split-BF16: n.(F- - F+) gets its own region and q- - q+ is recomputed
+  // (frees registers for the BF16 operands)
+  static constexpr bool DQ_LDS = PREC == PREC_BF16;
+  static constexpr int oD = oL + kTileE * 4;         // [NF quads][5][64]
+  static constexpr int total = oD + (DQ_LDS ? NF * 5 * kTileE : 0);
 };
 
 __device__ __forceinline__ double stage_time(double c, double t_host, double dt_host,
@@ -89,17 +103,28 @@ __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int N, int MODE, bool MOVING>
+__device__ __forceinline__ floatx4 mfma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// x = hi + lo + O(2^-16 |x|): hi = bf16(x), lo = bf16(x - hi), round to nearest even
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+template <int N, int MODE, bool MOVING, int PREC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel(DeviceMesh m, const float* __restrict__ q_in,
                                                          float* __restrict__ q_out,
                                                          float* __restrict__ res,
                                                          float* __restrict__ out, float a_rk,
                                                          float b_rk, double c_rk, double t_host,
                                                          double dt_host, const RunScalars* run) {
-  using S = Shape<N>;
+  using S = Shape<N, PREC>;
   constexpr int Np = S::Np, Nfp = S::Nfp, ST = S::ST, MT = S::MT, AS = S::AS, MP = S::MP;
   extern __shared__ float lds[];
-  const float* sA = S::A_LDS ? lds + S::oA : m.Aop;
+  // row k of the FP32 operator is sA[k * AS + col] (LDS holds rows >= AROW0)
+  const float* sA = S::A_LDS ? lds + S::oA - S::AROW0 * AS : m.Aop;
   uint8_t* sFm = reinterpret_cast<uint8_t*>(lds + S::oTab);
   uint8_t* sNN = sFm + S::NF;
   float* sQ = lds + S::oQ;
@@ -115,7 +140,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const int e = lane & 15, g = lane >> 4;
 
   if (S::A_LDS)
-    for (int i = tid; i < S::KT * AS; i += kThreads) lds[S::oA + i] = m.Aop[i];
+    for (int i = tid; i < (S::KT - S::AROW0) * AS; i += kThreads)
+      lds[S::oA + i] = m.Aop[S::AROW0 * AS + i];
   for (int i = tid; i < S::NF; i += kThreads) sFm[i] = m.fmask[i];
   for (int i = tid; i < 96 * Nfp; i += kThreads) sNN[i] = m.nbr_node[i];
 
@@ -240,7 +266,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     // B. surface: traces, face speeds and the normal-flux difference
     //    n.(F- - F+) (stored over the staged exterior trace); q- - q+ stays
     //    in registers for the contraction pass (same lanes, same quads)
-    float dq[kFQ][5];
+    float dq[S::DQ_LDS ? 1 : kFQ][5];
+    float* sD = lds + S::oD;
 #pragma unroll
     for (int kq = 0; kq < kFQ; ++kq) {
       const int fq = w + kWaves * kq;
@@ -269,10 +296,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       float fm[5], fp[5];
       normal_flux<MOVING>(P, wm, n, fm);
       normal_flux<MOVING>(P, wp, n, fp);
+      if (S::DQ_LDS) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        slot[v * 64] = fm[v] - fp[v];
-        dq[kq][v] = qm[v] - qp[v];
+        for (int v = 0; v < 5; ++v) {
+          sD[fq * 5 * 64 + lane + v * 64] = fm[v] - fp[v];
+          if (nb < 0) slot[v * 64] = qp[v];  // ghost state, for the recomputation
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          slot[v * 64] = fm[v] - fp[v];
+          dq[kq][v] = qm[v] - qp[v];
+        }
       }
     }
     __syncthreads();
@@ -287,35 +322,92 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     float gm[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) gm[i] = sMg[e * 9 + i];
-    for (int nq = (w + 1) % kWaves; nq < S::NNQ; nq += kWaves) {
-      const int j = 4 * nq + g;
-      float F[3][5];
-      if (j < Np && valid) {
-        float q[5];
+    if (PREC == PREC_BF16) {
+      // volume on BF16 MFMA: D (hi, lo) x F' (hi, lo), lo*lo dropped
+      const bf16x8* Ab = reinterpret_cast<const bf16x8*>(m.Abf);
+      for (int kb = w; kb < S::NKB; kb += kWaves) {
+        float F[2][3][5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) q[v] = sQ[e * ST + v * Np + j];
-        Prim wv;
-        primitive<MOVING>(P, q, wv);
+        for (int jj = 0; jj < 2; ++jj) {
+          const int j = 8 * kb + 2 * g + jj;
+          if (j < Np && valid) {
+            float q[5];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const float d[3] = {gm[a * 3 + 0], gm[a * 3 + 1], gm[a * 3 + 2]};
-          normal_flux<MOVING>(P, wv, d, F[a]);
+            for (int v = 0; v < 5; ++v) q[v] = sQ[e * ST + v * Np + j];
+            Prim wv;
+            primitive<MOVING>(P, q, wv);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const float d[3] = {gm[a * 3 + 0], gm[a * 3 + 1], gm[a * 3 + 2]};
+              normal_flux<MOVING>(P, wv, d, F[jj][a]);
+            }
+          } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+              for (int v = 0; v < 5; ++v) F[jj][a][v] = 0.0f;
+          }
         }
-      } else {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int v = 0; v < 5; ++v) F[a][v] = 0.0f;
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
+        bf16x8 Ahi[MT], Alo[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          const float av = sA[(a * S::NQP + j) * AS + mt * 16 + e];
-#pragma unroll
-          for (int v = 0; v < 5; ++v) acc[v][mt] = mfma(av, F[a][v], acc[v][mt]);
+          const int row = mt * 16 + e;
+          Ahi[mt] = Ab[(row * S::KVB + kb * 32 + 8 * g) / 8];
+          Alo[mt] = Ab[((MP + row) * S::KVB + kb * 32 + 8 * g) / 8];
         }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          bf16x8 Bhi, Blo;
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              __bf16 h, l;
+              split_bf16(F[jj][a][v], h, l);
+              Bhi[3 * jj + a] = h;
+              Blo[3 * jj + a] = l;
+            }
+          Bhi[6] = Bhi[7] = Blo[6] = Blo[7] = (__bf16)0.0f;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            acc[v][mt] = mfma_bf16(Ahi[mt], Bhi, acc[v][mt]);
+            acc[v][mt] = mfma_bf16(Ahi[mt], Blo, acc[v][mt]);
+            acc[v][mt] = mfma_bf16(Alo[mt], Bhi, acc[v][mt]);
+          }
+        }
+      }
+    } else {
+      for (int nq = (w + 1) % kWaves; nq < S::NNQ; nq += kWaves) {
+        const int j = 4 * nq + g;
+        float F[3][5];
+        if (j < Np && valid) {
+          float q[5];
+  #pragma unroll
+          for (int v = 0; v < 5; ++v) q[v] = sQ[e * ST + v * Np + j];
+          Prim wv;
+          primitive<MOVING>(P, q, wv);
+  #pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const float d[3] = {gm[a * 3 + 0], gm[a * 3 + 1], gm[a * 3 + 2]};
+            normal_flux<MOVING>(P, wv, d, F[a]);
+          }
+        } else {
+  #pragma unroll
+          for (int a = 0; a < 3; ++a)
+  #pragma unroll
+            for (int v = 0; v < 5; ++v) F[a][v] = 0.0f;
+        }
+  #pragma unroll
+        for (int a = 0; a < 3; ++a)
+  #pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const float av = sA[(a * S::NQP + j) * AS + mt * 16 + e];
+  #pragma unroll
+            for (int v = 0; v < 5; ++v) acc[v][mt] = mfma(av, F[a][v], acc[v][mt]);
+          }
+      }
     }
+
     // surface term: dF = Fscale/2 [n.(F- - F+) - lambda (q- - q+)]
 #pragma unroll
     for (int kq = 0; kq < kFQ; ++kq) {
@@ -326,8 +418,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       const float hs = valid ? 0.5f * sFg[e * 17 + f * 4 + 3] : 0.0f;
       const float* slot = sP + fq * 5 * 64 + lane;
       float dF[5];
+      if (S::DQ_LDS) {
+        const int node = sFm[i];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) dF[v] = hs * (slot[v * 64] - lam * dq[kq][v]);
+        for (int v = 0; v < 5; ++v)
+          dF[v] = hs * (sD[fq * 5 * 64 + lane + v * 64] -
+                        lam * (sQ[e * ST + v * Np + node] - slot[v * 64]));
+      } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) dF[v] = hs * (slot[v * 64] - lam * dq[kq][v]);
+      }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const float av = sA[(S::KV + i) * AS + mt * 16 + e];
@@ -464,53 +564,68 @@ __global__ void prim_kernel(DeviceMesh m, const float* __restrict__ in, float* _
   }
 }
 
-template <int N, int MODE, bool MOVING>
-hipError_t set_lds_limit(int lds) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<N, MODE, MOVING>),
+template <int N, int MODE, bool MOVING, int PREC>
+hipError_t set_lds_limit() {
+  const int lds = int(Shape<N, PREC>::total * sizeof(float));
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<N, MODE, MOVING, PREC>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
-template <int N>
-hipError_t stage_prepare(int* blocks_per_cu) {
-  using S = Shape<N>;
-  const int lds = int(S::total * sizeof(float));
-  hipError_t e = set_lds_limit<N, MODE_RHS, false>(lds);
-  if (e == hipSuccess) e = set_lds_limit<N, MODE_STAGE, false>(lds);
-  if (e == hipSuccess) e = set_lds_limit<N, MODE_RHS, true>(lds);
-  if (e == hipSuccess) e = set_lds_limit<N, MODE_STAGE, true>(lds);
+template <int N, int PREC>
+hipError_t stage_prepare_prec(int* blocks_per_cu) {
+  hipError_t e = set_lds_limit<N, MODE_RHS, false, PREC>();
+  if (e == hipSuccess) e = set_lds_limit<N, MODE_STAGE, false, PREC>();
+  if (e == hipSuccess) e = set_lds_limit<N, MODE_RHS, true, PREC>();
+  if (e == hipSuccess) e = set_lds_limit<N, MODE_STAGE, true, PREC>();
   if (e != hipSuccess) return e;
   int nb = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &nb, reinterpret_cast<const void*>(&stage_kernel<N, MODE_STAGE, true>), kThreads, lds);
+      &nb, reinterpret_cast<const void*>(&stage_kernel<N, MODE_STAGE, true, PREC>), kThreads,
+      Shape<N, PREC>::total * sizeof(float));
   if (e != hipSuccess) return e;
   *blocks_per_cu = std::max(nb, 1);
   return hipSuccess;
 }
 
-template <int N, int MODE, bool MOVING>
-void stage_launch(int blocks, size_t lds, hipStream_t s, const DeviceMesh& m, const float* q_in,
-                  float* q_out, float* res, float* out, float a, float b, double c,
-                  double t_host, double dt_host, const RunScalars* run) {
-  stage_kernel<N, MODE, MOVING><<<blocks, kThreads, lds, s>>>(m, q_in, q_out, res, out, a, b, c,
-                                                              t_host, dt_host, run);
+template <int N>
+hipError_t stage_prepare(int precision, int* blocks_per_cu) {
+  return precision == 1 ? stage_prepare_prec<N, PREC_BF16>(blocks_per_cu)
+                        : stage_prepare_prec<N, PREC_FP32>(blocks_per_cu);
+}
+
+template <int N, int MODE, bool MOVING, int PREC>
+void stage_launch(int blocks, hipStream_t s, const DeviceMesh& m, const float* q_in, float* q_out,
+                  float* res, float* out, float a, float b, double c, double t_host,
+                  double dt_host, const RunScalars* run) {
+  const size_t lds = size_t(Shape<N, PREC>::total) * sizeof(float);
+  stage_kernel<N, MODE, MOVING, PREC><<<blocks, kThreads, lds, s>>>(m, q_in, q_out, res, out, a, b,
+                                                                    c, t_host, dt_host, run);
+}
+
+template <int N, int PREC>
+void stage_launch_mode(int mode, bool moving, int blocks, hipStream_t s, const DeviceMesh& m,
+                       const float* q_in, float* q_out, float* res, float* out, float a, float b,
+                       double c, double t_host, double dt_host, const RunScalars* run) {
+  if (mode == MODE_RHS) {
+    if (moving) stage_launch<N, MODE_RHS, true, PREC>(blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+    else stage_launch<N, MODE_RHS, false, PREC>(blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+  } else {
+    if (moving) stage_launch<N, MODE_STAGE, true, PREC>(blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+    else stage_launch<N, MODE_STAGE, false, PREC>(blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+  }
 }
 
 template <int N>
 hipError_t stage_dispatch(const DeviceMesh& m, int mode, const float* q_in, float* q_out,
                           float* res, float* out, float a, float b, double c, double t_host,
                           double dt_host, const RunScalars* run, hipStream_t s) {
-  using S = Shape<N>;
   const int64_t tiles = (m.K + kTileE - 1) / kTileE;
   const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(tiles, int64_t(m.num_cu) * m.blocks_per_cu)));
-  const size_t lds = size_t(S::total) * sizeof(float);
   const bool moving = m.phys.u0[0] != 0.0f || m.phys.u0[1] != 0.0f || m.phys.u0[2] != 0.0f;
-  if (mode == MODE_RHS) {
-    if (moving) stage_launch<N, MODE_RHS, true>(blocks, lds, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
-    else stage_launch<N, MODE_RHS, false>(blocks, lds, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
-  } else {
-    if (moving) stage_launch<N, MODE_STAGE, true>(blocks, lds, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
-    else stage_launch<N, MODE_STAGE, false>(blocks, lds, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
-  }
+  if (m.precision == 1)
+    stage_launch_mode<N, PREC_BF16>(mode, moving, blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+  else
+    stage_launch_mode<N, PREC_FP32>(mode, moving, blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
   return hipGetLastError();
 }
 
@@ -557,6 +672,54 @@ std::vector<float> pack_operator(int N, const double* Dr, const double* Ds, cons
   }
 }
 
+static uint16_t to_bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+static float from_bf16(uint16_t h) {
+  const uint32_t u = uint32_t(h) << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+
+template <int N>
+std::vector<uint16_t> pack_operator_bf16_n(const double* Dr, const double* Ds, const double* Dt) {
+  using S = Shape<N, PREC_BF16>;
+  std::vector<uint16_t> A(size_t(2) * S::MP * S::KVB, 0);
+  const double* D[3] = {Dr, Ds, Dt};
+  for (int mrow = 0; mrow < S::Np; ++mrow)
+    for (int kb = 0; kb < S::NKB; ++kb)
+      for (int gg = 0; gg < 4; ++gg)
+        for (int jj = 0; jj < 2; ++jj)
+          for (int a = 0; a < 3; ++a) {
+            const int j = 8 * kb + 2 * gg + jj;
+            if (j >= S::Np) continue;
+            const float x = float(-D[a][size_t(mrow) * S::Np + j]);
+            const uint16_t hi = to_bf16_rne(x);
+            const uint16_t lo = to_bf16_rne(x - from_bf16(hi));
+            const size_t k = size_t(kb) * 32 + 8 * gg + 3 * jj + a;
+            A[size_t(mrow) * S::KVB + k] = hi;
+            A[(size_t(S::MP) + mrow) * S::KVB + k] = lo;
+          }
+  return A;
+}
+
+std::vector<uint16_t> pack_operator_bf16(int N, const double* Dr, const double* Ds,
+                                         const double* Dt) {
+  switch (N) {
+    case 1: return pack_operator_bf16_n<1>(Dr, Ds, Dt);
+    case 2: return pack_operator_bf16_n<2>(Dr, Ds, Dt);
+    case 3: return pack_operator_bf16_n<3>(Dr, Ds, Dt);
+    case 4: return pack_operator_bf16_n<4>(Dr, Ds, Dt);
+    case 5: return pack_operator_bf16_n<5>(Dr, Ds, Dt);
+    default: return {};
+  }
+}
+
 size_t stage_lds_bytes(int N) {
   switch (N) {
     case 1: return Shape<1>::total * sizeof(float);
@@ -568,13 +731,13 @@ size_t stage_lds_bytes(int N) {
   }
 }
 
-hipError_t prepare_kernels(int N, int* blocks_per_cu) {
+hipError_t prepare_kernels(int N, int precision, int* blocks_per_cu) {
   switch (N) {
-    case 1: return stage_prepare<1>(blocks_per_cu);
-    case 2: return stage_prepare<2>(blocks_per_cu);
-    case 3: return stage_prepare<3>(blocks_per_cu);
-    case 4: return stage_prepare<4>(blocks_per_cu);
-    case 5: return stage_prepare<5>(blocks_per_cu);
+    case 1: return stage_prepare<1>(precision, blocks_per_cu);
+    case 2: return stage_prepare<2>(precision, blocks_per_cu);
+    case 3: return stage_prepare<3>(precision, blocks_per_cu);
+    case 4: return stage_prepare<4>(precision, blocks_per_cu);
+    case 5: return stage_prepare<5>(precision, blocks_per_cu);
     default: return hipErrorInvalidValue;
   }
 }

@@ -18,7 +18,7 @@ struct DeviceMesh {
   int num_cu = 256;          // compute units of the device
   int blocks_per_cu = 1;     // resident stage blocks per CU
   const float* Aop = nullptr;       // contraction operator, layout from pack_operator
-  const uint16_t* Abf = nullptr;    // split-BF16 operator (hi, lo) when used
+  const uint16_t* Abf = nullptr;    // split-BF16 volume operator, layout from pack_operator_bf16
   const uint8_t* fmask = nullptr;   // [4][Nfp]
   const uint8_t* nbr_node = nullptr;  // [4][4][6][Nfp]
   const double* vgeo = nullptr;     // [K][9]   d(r,s,t)/d(x,y,z)
@@ -65,12 +65,17 @@ hipError_t launch_prim_to_state(const DeviceMesh& m, const float* prim, float* q
 
 // Raise the dynamic-LDS limit of the stage kernels of order N (call once
 // per process and device before any launch or capture).
-hipError_t prepare_kernels(int N, int* blocks_per_cu);
+hipError_t prepare_kernels(int N, int precision, int* blocks_per_cu);
 
 // The contraction operator A = [-Dr -Ds -Dt | LIFT] of order N, transposed
 // and padded in the layout the stage kernel reads (FP32).
 std::vector<float> pack_operator(int N, const double* Dr, const double* Ds, const double* Dt,
                                  const double* LIFT);
+
+// Split-BF16 volume operator -[Dr Ds Dt]: hi = bf16(x), lo = bf16(x - hi),
+// laid out [hi|lo][MP][k-blocks of 32] as the split-BF16 stage kernel reads it.
+std::vector<uint16_t> pack_operator_bf16(int N, const double* Dr, const double* Ds,
+                                         const double* Dt);
 
 // Bytes of dynamic LDS one stage block uses at order N (0 if unsupported).
 size_t stage_lds_bytes(int N);
