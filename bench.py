@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--form", choices=("fp32", "bf16"), default="fp32")
     ap.add_argument("--kernel-iters", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the element-partitioned multi-GPU path "
@@ -153,6 +155,13 @@ def main():
     nbytes = stage_bytes(K, Np, True)
     achieved = nbytes / kernel_s / 1e9
     traffic = measured_traffic(args.form, K)
+    if args.copy_mb:
+        n = args.copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     out = {
         "metric": "DOF-stage updates/s",

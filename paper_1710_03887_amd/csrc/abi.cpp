@@ -165,12 +165,14 @@ int build_device(dg_ctx* c, hipStream_t s) {
 // context buffer; returns with the state in q when `end_in_q`, which needs
 // an even number of stage swaps in total (handled by the caller).
 hipError_t enqueue_stages(dg_ctx* c, float* q, float* res, bool start_in_q, double t, double dt,
-                          const dg::RunScalars* run, hipStream_t s) {
+                          dg::RunScalars* run, hipStream_t s) {
   float* bufs[2] = {q, c->qbuf};
   int cur = start_in_q ? 0 : 1;
   for (int i = 0; i < 5; ++i) {
+    // the last stage of a run step also reduces the next step's CFL rate
     hipError_t e = dg::launch_stage(c->dm, dg::MODE_STAGE, bufs[cur], bufs[1 - cur], res, nullptr,
-                                    float(kRK4a[i]), float(kRK4b[i]), kRK4c[i], t, dt, run, s);
+                                    float(kRK4a[i]), float(kRK4b[i]), kRK4c[i], t, dt, run,
+                                    i == 4 ? 1 : 0, s);
     if (e != hipSuccess) return e;
     cur = 1 - cur;
   }
@@ -293,7 +295,7 @@ int dg_rhs(dg_ctx* c, const float* q, float* rhs, double t, void* stream) {
   if (rc) return rc;
   if (!q || !rhs) return fail(c, DG_EINVAL, "null state pointer");
   hipError_t e = dg::launch_stage(c->dm, dg::MODE_RHS, q, nullptr, nullptr, rhs, 0.f, 0.f, 0.0, t,
-                                  0.0, nullptr, static_cast<hipStream_t>(stream));
+                                  0.0, nullptr, 0, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? DG_OK : hip_fail(c, e, "stage launch");
 }
 
@@ -317,7 +319,7 @@ int dg_stage(dg_ctx* c, const float* q_in, float* q_out, float* res, double a, d
   if (!q_in || !q_out || !res) return fail(c, DG_EINVAL, "null state pointer");
   if (q_in == q_out) return fail(c, DG_EINVAL, "q_in and q_out must differ");
   hipError_t e = dg::launch_stage(c->dm, dg::MODE_STAGE, q_in, q_out, res, nullptr, float(a),
-                                  float(b), 0.0, t_stage, dt, nullptr,
+                                  float(b), 0.0, t_stage, dt, nullptr, 0,
                                   static_cast<hipStream_t>(stream));
   return e == hipSuccess ? DG_OK : hip_fail(c, e, "stage launch");
 }
@@ -358,6 +360,11 @@ int dg_run(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double* 
                                 hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
 
+  // the first step's CFL rate; every later one comes from the last stage
+  // of the step before
+  e = dg::launch_rate(c->dm, q, c->run, s);
+  if (e != hipSuccess) return hip_fail(c, e, "rate launch");
+
   // a graph of two steps (ten stage swaps) leaves the state in q
   if (nsteps >= 2 && (c->two_steps.q != q || c->two_steps.res != res || !c->two_steps.exec)) {
     if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
@@ -367,9 +374,7 @@ int dg_run(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double* 
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
     hipError_t le = hipSuccess;
     for (int k = 0; k < 2 && le == hipSuccess; ++k) {
-      const float* qs = (k == 0) ? q : c->qbuf;
-      le = dg::launch_rate(c->dm, qs, c->run, cs);
-      if (le == hipSuccess) le = dg::launch_finalize(c->run, cs);
+      le = dg::launch_finalize(c->run, cs);
       if (le == hipSuccess) le = enqueue_stages(c, q, res, k == 0, 0.0, 0.0, c->run, cs);
       if (le == hipSuccess) le = dg::launch_advance(c->run, cs);
     }
@@ -393,8 +398,7 @@ int dg_run(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double* 
     if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
   }
   if (nsteps % 2 == 1) {
-    e = dg::launch_rate(c->dm, q, c->run, s);
-    if (e == hipSuccess) e = dg::launch_finalize(c->run, s);
+    e = dg::launch_finalize(c->run, s);
     if (e == hipSuccess) e = enqueue_stages(c, q, res, true, 0.0, 0.0, c->run, s);
     if (e == hipSuccess) e = dg::launch_advance(c->run, s);
     if (e == hipSuccess)

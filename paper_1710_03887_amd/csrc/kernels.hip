@@ -119,7 +119,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                                                          float* __restrict__ res,
                                                          float* __restrict__ out, float a_rk,
                                                          float b_rk, double c_rk, double t_host,
-                                                         double dt_host, const RunScalars* run) {
+                                                         double dt_host, RunScalars* run,
+                                                         int rate_out) {
   using S = Shape<N, PREC>;
   constexpr int Np = S::Np, Nfp = S::Nfp, ST = S::ST, MT = S::MT, AS = S::AS, MP = S::MP;
   extern __shared__ float lds[];
@@ -196,6 +197,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   __syncthreads();  // tables in LDS
   gather_offsets(c0 + jb);
 
+  float rate_best = 0.0f;   // time-step reduction over this block's tiles
+  unsigned rate_bad = 0u;
   for (int64_t tile = c0 + jb; tile < c1; tile += Gx) {
     const int64_t k0 = tile * kTileE;
     const int ne = int(min<int64_t>(kTileE, m.K - k0));
@@ -470,10 +473,67 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
           out[gidx[i]] = sum[i];
         } else {
           const float rr = dt * sum[i] + a_rk * rv[i];
+          const float qn = qv[i] + b_rk * rr;
           res[gidx[i]] = rr;
-          q_out[gidx[i]] = qv[i] + b_rk * rr;
+          q_out[gidx[i]] = qn;
+          if (rate_out) {  // same thread, same element/variable/node: in place
+            const int o = tid + i * kThreads;
+            const int eo = o / MP, node = o - eo * MP;
+            sQ[eo * ST + v * Np + node] = qn;
+          }
         }
       }
+    }
+
+    // time-step rule for the next step, from the new state (last stage only):
+    // max over face nodes of (N+1)^2/2 Fscale (|u| + c); non-physical states flagged
+    if (MODE == MODE_STAGE && rate_out) {
+      __syncthreads();
+      for (int it = tid; it < kTileE * S::NF; it += kThreads) {
+        const int eo = it / S::NF, i = it - eo * S::NF, f = i / Nfp;
+        if (eo >= ne) continue;
+        const int node = sFm[i];
+        float qq[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qq[v] = sQ[eo * ST + v * Np + node];
+        Prim wv;
+        primitive<MOVING>(P, qq, wv);
+        float sp2 = 0.0f;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const float u = P.u0[d] + wv.du[d];
+          sp2 += u * u;
+        }
+        const float rate = P.half_N1sq * sFg[eo * 17 + f * 4 + 3] *
+                           (sqrtf(sp2) + sqrtf(P.gamma * wv.p / wv.rho));
+        if (!(wv.rho > 0.0f) || !(wv.p > 0.0f) || !(rate == rate)) rate_bad = 1u;
+        else rate_best = fmaxf(rate_best, rate);
+      }
+    }
+  }
+
+  if (MODE == MODE_STAGE && rate_out) {
+    // one atomic per block: wavefront max, then across the block's wavefronts
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      rate_best = fmaxf(rate_best, __shfl_xor(rate_best, off));
+      rate_bad |= __shfl_xor(rate_bad, off);
+    }
+    __syncthreads();
+    if (lane == 0) {
+      sL[2 * w] = __float_as_uint(rate_best);
+      sL[2 * w + 1] = rate_bad;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      float b = 0.0f;
+      unsigned bd = 0u;
+      for (int ww = 0; ww < kWaves; ++ww) {
+        b = fmaxf(b, __uint_as_float(sL[2 * ww]));
+        bd |= sL[2 * ww + 1];
+      }
+      atomicMax(&run->rate_bits, __float_as_uint(b));
+      if (bd) atomicOr(&run->bad, 1u);
     }
   }
 }
@@ -596,36 +656,38 @@ hipError_t stage_prepare(int precision, int* blocks_per_cu) {
 template <int N, int MODE, bool MOVING, int PREC>
 void stage_launch(int blocks, hipStream_t s, const DeviceMesh& m, const float* q_in, float* q_out,
                   float* res, float* out, float a, float b, double c, double t_host,
-                  double dt_host, const RunScalars* run) {
+                  double dt_host, RunScalars* run, int rate_out) {
   const size_t lds = size_t(Shape<N, PREC>::total) * sizeof(float);
   stage_kernel<N, MODE, MOVING, PREC><<<blocks, kThreads, lds, s>>>(m, q_in, q_out, res, out, a, b,
-                                                                    c, t_host, dt_host, run);
+                                                                    c, t_host, dt_host, run,
+                                                                    rate_out);
 }
 
 template <int N, int PREC>
 void stage_launch_mode(int mode, bool moving, int blocks, hipStream_t s, const DeviceMesh& m,
                        const float* q_in, float* q_out, float* res, float* out, float a, float b,
-                       double c, double t_host, double dt_host, const RunScalars* run) {
+                       double c, double t_host, double dt_host, RunScalars* run, int rate_out) {
   if (mode == MODE_RHS) {
-    if (moving) stage_launch<N, MODE_RHS, true, PREC>(blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
-    else stage_launch<N, MODE_RHS, false, PREC>(blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+    if (moving) stage_launch<N, MODE_RHS, true, PREC>(blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, 0);
+    else stage_launch<N, MODE_RHS, false, PREC>(blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, 0);
   } else {
-    if (moving) stage_launch<N, MODE_STAGE, true, PREC>(blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
-    else stage_launch<N, MODE_STAGE, false, PREC>(blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+    if (moving) stage_launch<N, MODE_STAGE, true, PREC>(blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out);
+    else stage_launch<N, MODE_STAGE, false, PREC>(blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out);
   }
 }
 
 template <int N>
 hipError_t stage_dispatch(const DeviceMesh& m, int mode, const float* q_in, float* q_out,
                           float* res, float* out, float a, float b, double c, double t_host,
-                          double dt_host, const RunScalars* run, hipStream_t s) {
+                          double dt_host, RunScalars* run, int rate_out, hipStream_t s) {
   const int64_t tiles = (m.K + kTileE - 1) / kTileE;
   const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(tiles, int64_t(m.num_cu) * m.blocks_per_cu)));
   const bool moving = m.phys.u0[0] != 0.0f || m.phys.u0[1] != 0.0f || m.phys.u0[2] != 0.0f;
+  const int ro = (run != nullptr && rate_out) ? 1 : 0;
   if (m.precision == 1)
-    stage_launch_mode<N, PREC_BF16>(mode, moving, blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+    stage_launch_mode<N, PREC_BF16>(mode, moving, blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, ro);
   else
-    stage_launch_mode<N, PREC_FP32>(mode, moving, blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run);
+    stage_launch_mode<N, PREC_FP32>(mode, moving, blocks, s, m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, ro);
   return hipGetLastError();
 }
 
@@ -744,13 +806,13 @@ hipError_t prepare_kernels(int N, int precision, int* blocks_per_cu) {
 
 hipError_t launch_stage(const DeviceMesh& m, int mode, const float* q_in, float* q_out, float* res,
                         float* out, float a, float b, double c, double t_host, double dt_host,
-                        const RunScalars* run, hipStream_t s) {
+                        RunScalars* run, int rate_out, hipStream_t s) {
   switch (m.N) {
-    case 1: return stage_dispatch<1>(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, s);
-    case 2: return stage_dispatch<2>(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, s);
-    case 3: return stage_dispatch<3>(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, s);
-    case 4: return stage_dispatch<4>(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, s);
-    case 5: return stage_dispatch<5>(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, s);
+    case 1: return stage_dispatch<1>(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out, s);
+    case 2: return stage_dispatch<2>(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out, s);
+    case 3: return stage_dispatch<3>(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out, s);
+    case 4: return stage_dispatch<4>(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out, s);
+    case 5: return stage_dispatch<5>(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -45,10 +45,12 @@ enum StageMode : int { MODE_RHS = 0, MODE_STAGE = 1 };
 // One right-hand-side evaluation (MODE_RHS: out = f(q_in)) or one fused
 // low-storage RK stage (MODE_STAGE: res = a res + dt f(q_in);
 // q_out = q_in + b res).  Time is t_host + c dt_host, or read from
-// run->t/run->dt when `run` is not null.
+// run->t/run->dt when `run` is not null.  With run and rate_out set (last
+// stage of a step), the stage also reduces the next step's time-step rate
+// from q_out into run->rate_bits and flags non-physical states.
 hipError_t launch_stage(const DeviceMesh& m, int mode, const float* q_in, float* q_out,
                         float* res, float* out, float a, float b, double c, double t_host,
-                        double dt_host, const RunScalars* run, hipStream_t s);
+                        double dt_host, RunScalars* run, int rate_out, hipStream_t s);
 
 // Max of (N+1)^2/2 Fscale (|u|+c) over interior face traces into
 // run->rate_bits (as ordered float bits); flags non-physical traces.
