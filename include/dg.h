@@ -210,6 +210,50 @@ int dg_prim_to_state(dg_ctx* ctx, const float* prim, float* q, void* stream);
 /* Inverse of dg_prim_to_state. */
 int dg_state_to_prim(dg_ctx* ctx, const float* q, float* prim, void* stream);
 
+/* ---- batched ensembles ---------------------------------------------------
+ * Several geometries (contexts created with the same N, gamma and ambient
+ * state) times up to 16 members that differ by their inflow-pulse amplitude,
+ * advanced together by one persistent stage kernel per RK stage, captured in
+ * one HIP graph.  Member states are stored member-innermost:
+ * FP32 [K_g][5][Np][16] per geometry g (slots >= members are ignored), as
+ * perturbations about the ambient state like single states.
+ */
+typedef struct dg_batch dg_batch;
+
+/* Bind ngeom contexts (borrowed: they must outlive the batch) with
+ * `members` (1..16) members each.  Errors: DG_EINVAL on mismatched N or
+ * physics, DG_ENOMEM, DG_EHIP. */
+int dg_batch_create(dg_ctx* const* geoms, int ngeom, int members, void* stream,
+                    dg_batch** out);
+
+int dg_batch_destroy(dg_batch* b);
+
+const char* dg_batch_last_error(const dg_batch* b);
+
+/*
+ * nsteps steps of every member, each with its own time step from the CFL
+ * rule of dg_run and its own time.  q[g], res[g]: device FP32
+ * [K_g][5][Np][16]; amps: host double [ngeom][16] inflow amplitudes;
+ * t_inout: host double [ngeom][16] start times in, end times out.
+ * Synchronizes once at the end.  Returns DG_ENONPHYS when any member met a
+ * non-physical state (dg_batch_first_bad gives the steps).
+ */
+int dg_batch_run(dg_batch* b, float* const* q, float* const* res, const double* amps,
+                 int64_t nsteps, double cfl, double* t_inout, void* stream);
+
+/* First non-physical step per member in the last dg_batch_run, or -1:
+ * host int64 [ngeom][16]. */
+int dg_batch_first_bad(const dg_batch* b, int64_t* steps);
+
+/* Launch shape of the batched stage kernel: resident blocks per CU
+ * (0 = as many as fit) and wavefronts per block (1, 2, 4 or 8).  Used by
+ * the autotuner; takes effect at the next dg_batch_run. */
+int dg_batch_set_launch(dg_batch* b, int blocks_per_cu, int waves_per_block);
+
+/* Resident stage blocks per CU of a single-solve context (0 = as many as
+ * fit); used by the autotuner. */
+int dg_set_launch(dg_ctx* ctx, int blocks_per_cu);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,15 @@ _SIGS = {
     "dg_stable_dt": (ctypes.c_int, [_vp, _vp, _f64, ctypes.POINTER(_f64), _vp]),
     "dg_prim_to_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "dg_state_to_prim": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "dg_set_launch": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "dg_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp,
+                                       ctypes.POINTER(_vp)]),
+    "dg_batch_destroy": (ctypes.c_int, [_vp]),
+    "dg_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "dg_batch_run": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _i64, _f64,
+                                    _vp, _vp]),
+    "dg_batch_first_bad": (ctypes.c_int, [_vp, _vp]),
+    "dg_batch_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -251,3 +260,96 @@ def dg_state_to_prim(ctx, q, prim, stream=None):
     _check_state(ctx, q, "q")
     _check_state(ctx, prim, "prim")
     _check(_lib.dg_state_to_prim(ctx.handle, _ptr(q), _ptr(prim), _stream(stream)), ctx.handle)
+
+
+def dg_set_launch(ctx, blocks_per_cu):
+    _check(_lib.dg_set_launch(ctx.handle, int(blocks_per_cu)), ctx.handle)
+
+
+# ---- batched ensembles --------------------------------------------------------
+MEMBERS = 16
+
+
+class Batch:
+    """Owns a dg_batch handle; keeps its contexts alive."""
+
+    def __init__(self, handle, geoms, members):
+        self.handle = handle
+        self.geoms = list(geoms)
+        self.members = members
+
+    def close(self):
+        if self.handle:
+            _lib.dg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _bcheck(code, b):
+    if code != DG_OK:
+        msg = _lib.dg_batch_last_error(b.handle if b is not None else None)
+        raise DGError(code, msg.decode() if msg else "")
+
+
+def dg_batch_create(geoms, members=MEMBERS, stream=None):
+    arr = (_vp * len(geoms))(*[g.handle for g in geoms])
+    h = _vp()
+    code = _lib.dg_batch_create(arr, len(geoms), int(members), _stream(stream), ctypes.byref(h))
+    if code != DG_OK:
+        raise DGError(code, "dg_batch_create: contexts must be device contexts with the same N "
+                            "and ambient state; 1 <= members <= 16")
+    return Batch(h, geoms, members)
+
+
+def dg_batch_destroy(b):
+    b.close()
+
+
+def dg_batch_last_error(b):
+    msg = _lib.dg_batch_last_error(b.handle)
+    return msg.decode() if msg else ""
+
+
+def _check_batch_state(ctx, x, name):
+    shape = (ctx.K, 5, ctx.Np, MEMBERS)
+    if x is None or tuple(x.shape) != shape:
+        raise ValueError(f"{name} must have shape {shape}")
+    if str(x.dtype) != "torch.float32" or not x.is_cuda or not x.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
+
+
+def dg_batch_run(b, q, res, amps, nsteps, cfl, t=None, stream=None):
+    """q, res: one [K_g, 5, Np, 16] float32 device tensor per geometry;
+    amps: [ngeom, 16] inflow amplitudes; t: [ngeom, 16] start times (zeros
+    when None).  Returns the end times [ngeom, 16].  Raises
+    DGError(DG_ENONPHYS) when a member met a non-physical state
+    (dg_batch_first_bad names the steps)."""
+    ng = len(b.geoms)
+    if len(q) != ng or len(res) != ng:
+        raise ValueError("one state and one residual per geometry")
+    for g, ctx in enumerate(b.geoms):
+        _check_batch_state(ctx, q[g], f"q[{g}]")
+        _check_batch_state(ctx, res[g], f"res[{g}]")
+    amps = np.ascontiguousarray(np.broadcast_to(np.asarray(amps, dtype=np.float64), (ng, MEMBERS)))
+    tt = np.zeros((ng, MEMBERS)) if t is None else np.array(np.broadcast_to(t, (ng, MEMBERS)),
+                                                               dtype=np.float64)
+    qp = (_vp * ng)(*[x.data_ptr() for x in q])
+    rp = (_vp * ng)(*[x.data_ptr() for x in res])
+    _bcheck(_lib.dg_batch_run(b.handle, qp, rp, amps.ctypes.data, int(nsteps), float(cfl),
+                              tt.ctypes.data, _stream(stream)), b)
+    return tt
+
+
+def dg_batch_first_bad(b):
+    out = np.full((len(b.geoms), MEMBERS), -1, dtype=np.int64)
+    _bcheck(_lib.dg_batch_first_bad(b.handle, out.ctypes.data), b)
+    return out
+
+
+def dg_batch_set_launch(b, blocks_per_cu, waves_per_block):
+    _bcheck(_lib.dg_batch_set_launch(b.handle, int(blocks_per_cu), int(waves_per_block)), b)

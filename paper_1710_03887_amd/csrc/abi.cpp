@@ -2,6 +2,7 @@
 // the HIP-graph-captured run loop.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -9,46 +10,13 @@
 #include <vector>
 
 #include "../../include/dg.h"
-#include "kernels.hpp"
-#include "setup.hpp"
+#include "ctx.hpp"
 
 namespace {
 
 thread_local std::string g_setup_error;
 
-// Five-stage low-storage RK coefficients (Carpenter & Kennedy 1994).
-const double kRK4a[5] = {0.0, -567301805773.0 / 1357537059087.0,
-                         -2404267990393.0 / 2016746695238.0, -3550918686646.0 / 2091501179385.0,
-                         -1275806237668.0 / 842570457699.0};
-const double kRK4b[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
-                         1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
-                         2277821191437.0 / 14882151754819.0};
-const double kRK4c[5] = {0.0, 1432997174477.0 / 9575080441755.0,
-                         2526269341429.0 / 6820363962896.0, 2006345519317.0 / 3224310063776.0,
-                         2802321613138.0 / 2924317926251.0};
-
-struct GraphCache {
-  hipGraphExec_t exec = nullptr;
-  const float* q = nullptr;
-  const float* res = nullptr;
-};
-
 }  // namespace
-
-struct dg_ctx {
-  std::string err;
-  bool host_only = false;
-  dg::RefOps ops;
-  dg::HostMesh mesh;
-  dg::DeviceMesh dm;
-  std::vector<void*> allocs;
-  float* qbuf = nullptr;            // ping-pong partner of the caller's state
-  dg::RunScalars* run = nullptr;    // device scalars
-  dg::RunScalars host_run{};        // staging for uploads/downloads
-  hipStream_t capture_stream = nullptr;
-  GraphCache two_steps;
-  int64_t last_bad = -1;
-};
 
 namespace {
 
@@ -78,7 +46,7 @@ int upload(dg_ctx* c, const T* host, size_t n, T** dev, hipStream_t s) {
 
 void free_device(dg_ctx* c) {
   if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
-  c->two_steps = GraphCache{};
+  c->two_steps = dg::GraphCache{};
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -115,6 +83,7 @@ int build_device(dg_ctx* c, hipStream_t s) {
 
   hipError_t e = dg::prepare_kernels(c->dm.N, c->dm.precision, &c->dm.blocks_per_cu);
   if (e != hipSuccess) return hip_fail(c, e, "stage kernel attributes");
+  c->max_blocks_per_cu = c->dm.blocks_per_cu;
   int dev = 0;
   e = hipGetDevice(&dev);
   if (e == hipSuccess)
@@ -171,7 +140,7 @@ hipError_t enqueue_stages(dg_ctx* c, float* q, float* res, bool start_in_q, doub
   for (int i = 0; i < 5; ++i) {
     // the last stage of a run step also reduces the next step's CFL rate
     hipError_t e = dg::launch_stage(c->dm, dg::MODE_STAGE, bufs[cur], bufs[1 - cur], res, nullptr,
-                                    float(kRK4a[i]), float(kRK4b[i]), kRK4c[i], t, dt, run,
+                                    float(dg::kRK4a[i]), float(dg::kRK4b[i]), dg::kRK4c[i], t, dt, run,
                                     i == 4 ? 1 : 0, s);
     if (e != hipSuccess) return e;
     cur = 1 - cur;
@@ -368,7 +337,7 @@ int dg_run(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double* 
   // a graph of two steps (ten stage swaps) leaves the state in q
   if (nsteps >= 2 && (c->two_steps.q != q || c->two_steps.res != res || !c->two_steps.exec)) {
     if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
-    c->two_steps = GraphCache{};
+    c->two_steps = dg::GraphCache{};
     hipStream_t cs = c->capture_stream;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
@@ -417,6 +386,17 @@ int dg_run(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double* 
 }
 
 int64_t dg_last_step(const dg_ctx* c) { return c ? c->last_bad : -1; }
+
+int dg_set_launch(dg_ctx* c, int blocks_per_cu) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (blocks_per_cu < 0) return fail(c, DG_EINVAL, "blocks_per_cu must be >= 0");
+  c->dm.blocks_per_cu = blocks_per_cu == 0 ? c->max_blocks_per_cu
+                                           : std::min(blocks_per_cu, c->max_blocks_per_cu);
+  if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
+  c->two_steps = dg::GraphCache{};
+  return DG_OK;
+}
 
 int dg_prim_to_state(dg_ctx* c, const float* prim, float* q, void* stream) {
   int rc = need_device(c);

@@ -1,0 +1,54 @@
+// Host-side state of a context, shared by the single-solve and batched C ABI
+// translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "setup.hpp"
+
+namespace dg {
+
+// Five-stage, fourth-order low-storage RK coefficients (Carpenter & Kennedy
+// 1994), 2N-storage form: res = a_i res + dt L(q, t + c_i dt); q += b_i res.
+constexpr double kRK4a[5] = {0.0, -567301805773.0 / 1357537059087.0,
+                             -2404267990393.0 / 2016746695238.0,
+                             -3550918686646.0 / 2091501179385.0,
+                             -1275806237668.0 / 842570457699.0};
+constexpr double kRK4b[5] = {1432997174477.0 / 9575080441755.0,
+                             5161836677717.0 / 13612068292357.0,
+                             1720146321549.0 / 2090206949498.0,
+                             3134564353537.0 / 4481467310338.0,
+                             2277821191437.0 / 14882151754819.0};
+constexpr double kRK4c[5] = {0.0, 1432997174477.0 / 9575080441755.0,
+                             2526269341429.0 / 6820363962896.0,
+                             2006345519317.0 / 3224310063776.0,
+                             2802321613138.0 / 2924317926251.0};
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  const float* q = nullptr;
+  const float* res = nullptr;
+};
+
+}  // namespace dg
+
+struct dg_ctx {
+  std::string err;
+  int max_blocks_per_cu = 1;        // occupancy limit of the stage kernel
+  bool host_only = false;
+  dg::RefOps ops;
+  dg::HostMesh mesh;
+  dg::DeviceMesh dm;
+  std::vector<void*> allocs;
+  float* qbuf = nullptr;            // ping-pong partner of the caller's state
+  dg::RunScalars* run = nullptr;    // device scalars
+  dg::RunScalars host_run{};        // staging for uploads/downloads
+  hipStream_t capture_stream = nullptr;
+  dg::GraphCache two_steps;
+  int64_t last_bad = -1;
+};
