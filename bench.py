@@ -91,6 +91,102 @@ def cpu_baseline(seconds_budget=30.0):
                       f"BLAS threads={threads}, host cores={os.cpu_count()}"}
 
 
+def time_single(dg, torch, m, N, form, steps, warmup, kernel_iters):
+    """One solve on mesh m: timed dg_run plus the stage kernel timed alone."""
+    amp, alpha, p0 = 0.1 / 1.4, 2 * np.pi * 565.0 / 343.0, 1.0 / 1.4
+    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, gamma=1.4, rho0=1.0, p0=p0,
+                           inflow_amp=amp, inflow_alpha=alpha,
+                           precision={"fp32": dg.DG_FP32, "bf16": dg.DG_SPLIT_BF16}[form])
+    K, Np = ctx.K, ctx.Np
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    q = torch.zeros((K, 5, Np), dtype=torch.float32, device=dev)   # fluid at rest
+    res = torch.zeros_like(q)
+    bpc = dg.dg_autotune(ctx, q, res, None, stream=stream)
+
+    t, _ = dg.dg_run(ctx, q, res, warmup, 0.5, 0.0, stream=stream)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record(stream)
+    t_end, dt_last = dg.dg_run(ctx, q, res, steps, 0.5, t, stream=stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = start.elapsed_time(stop)
+    dof = 5 * K * Np
+
+    # dominant kernel: the fused stage, timed alone on the same stream
+    qb = torch.empty_like(q)
+    for _ in range(3):
+        dg.dg_stage(ctx, q, qb, res, RK4A2, RK4B2, t_end, dt_last, stream=stream)
+    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k0.record(stream)
+    for i in range(kernel_iters):
+        src, dst = (q, qb) if i % 2 == 0 else (qb, q)
+        dg.dg_stage(ctx, src, dst, res, RK4A2, RK4B2, t_end, dt_last, stream=stream)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    kernel_s = k0.elapsed_time(k1) * 1e-3 / kernel_iters
+    nbytes = stage_bytes(K, Np, True)
+    return {"K": K, "N": N, "Np": Np, "dof": dof, "ms": ms, "wall_s": wall, "t_end": t_end,
+            "dt_last": dt_last, "value": dof * 5 * steps / (ms * 1e-3), "kernel_s": kernel_s,
+            "bytes": nbytes, "achieved": nbytes / kernel_s / 1e9, "blocks_per_cu": bpc}
+
+
+def batch_stage_bytes(Ks, Np, members=16):
+    """Algorithmic HBM bytes of one batched stage: four FP32 state passes
+    per member-innermost DOF plus each element's geometry and connectivity
+    read once for all members."""
+    return sum(K * (4 * 5 * Np * members * 4 + (9 + 16) * 8 + 4 * 4 + 4) for K in Ks)
+
+
+def time_batch(dg, torch, steps, warmup, kernel_iters, scale=1.0):
+    """The ensemble: full box (50k), sphere of radius 1.5 (80k) and half
+    domain (30k) around the trumpet, 16 pulse amplitudes log-spaced over
+    0.1%-10% of p0 each, N = 3, FP32, launch shape from the autotuner."""
+    from workloads import trumpet_domain
+    p0, alpha, N = 1.0 / 1.4, 2 * np.pi * 565.0 / 343.0, 3
+    meshes = [trumpet_domain(kind, int(n * scale))
+              for kind, n in (("box", 50_000), ("sphere", 80_000), ("half", 30_000))]
+    ctxs = [dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, gamma=1.4, rho0=1.0, p0=p0,
+                             inflow_amp=0.0, inflow_alpha=alpha) for m in meshes]
+    Ks, Np = [c.K for c in ctxs], ctxs[0].Np
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    b = dg.dg_batch_create(ctxs, 16)
+    q = [torch.zeros((K, 5, Np, 16), dtype=torch.float32, device=dev) for K in Ks]
+    res = [torch.zeros_like(x) for x in q]
+    amps = p0 * np.logspace(-3, -1, 16)
+    bpc, waves = dg.dg_batch_autotune(b, q, res, None, stream=stream)
+    t = dg.dg_batch_run(b, q, res, amps, warmup, 0.5, None, stream=stream)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    t = dg.dg_batch_run(b, q, res, amps, steps, 0.5, t, stream=stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    dof = 5 * Np * 16 * sum(Ks)
+    # per-stage average over whole steps (the two one-block scalar kernels of
+    # each step and one start-of-run rate pass included)
+    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k0.record(stream)
+    t = dg.dg_batch_run(b, q, res, amps, kernel_iters, 0.5, t, stream=stream)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    step_s = k0.elapsed_time(k1) * 1e-3 / kernel_iters
+    nbytes = batch_stage_bytes(Ks, Np)
+    return {"K": Ks, "N": N, "Np": Np, "members": 16, "dof": dof, "ms": ms,
+            "value": dof * 5 * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+            "blocks_per_cu": bpc, "waves_per_block": waves, "bytes_per_stage": nbytes,
+            "stage_ms_step_avg": step_s / 5 * 1e3,
+            "achieved_GBs_step_avg": nbytes * 5 / step_s / 1e9,
+            "frac_step_avg": nbytes * 5 / step_s / 1e9 / HBM_PEAK_GBS,
+            "t_min": float(t.min()), "t_max": float(t.max())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,7 +194,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--elements", type=int, default=200_000, help="target tetrahedra")
     ap.add_argument("--order", type=int, default=4)
-    ap.add_argument("--form", choices=("fp32", "bf16"), default="fp32")
+    ap.add_argument("--form", choices=("fp32", "bf16"), default="fp32",
+                    help="form of the headline measurement")
+    ap.add_argument("--also", default="bf16,batch",
+                    help="comma list of extra measurements: bf16, fp32, batch (or empty)")
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--kernel-iters", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -116,48 +216,23 @@ def main():
 
     m = trumpet_domain("box", args.elements)
     N = args.order
-    amp, alpha, p0 = 0.1 / 1.4, 2 * np.pi * 565.0 / 343.0, 1.0 / 1.4
-    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, gamma=1.4, rho0=1.0, p0=p0,
-                           inflow_amp=amp, inflow_alpha=alpha,
-                           precision={"fp32": dg.DG_FP32, "bf16": dg.DG_SPLIT_BF16}[args.form])
-    K, Np = ctx.K, ctx.Np
-    dev = torch.device("cuda", 0)
-    stream = torch.cuda.current_stream(dev)
-    q = torch.zeros((K, 5, Np), dtype=torch.float32, device=dev)   # fluid at rest
-    res = torch.zeros_like(q)
-
-    t, _ = dg.dg_run(ctx, q, res, args.warmup, 0.5, 0.0, stream=stream)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    start.record(stream)
-    t_end, dt_last = dg.dg_run(ctx, q, res, args.steps, 0.5, t, stream=stream)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = start.elapsed_time(stop)
-    dof = 5 * K * Np
-    value = dof * 5 * args.steps / (ms * 1e-3)
-
-    # dominant kernel: the fused stage, timed alone on the same stream
-    qb = torch.empty_like(q)
-    for _ in range(3):
-        dg.dg_stage(ctx, q, qb, res, RK4A2, RK4B2, t_end, dt_last, stream=stream)
-    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    k0.record(stream)
-    for i in range(args.kernel_iters):
-        src, dst = (q, qb) if i % 2 == 0 else (qb, q)
-        dg.dg_stage(ctx, src, dst, res, RK4A2, RK4B2, t_end, dt_last, stream=stream)
-    k1.record(stream)
-    torch.cuda.synchronize()
-    kernel_s = k0.elapsed_time(k1) * 1e-3 / args.kernel_iters
-    nbytes = stage_bytes(K, Np, True)
-    achieved = nbytes / kernel_s / 1e9
+    r = time_single(dg, torch, m, N, args.form, args.steps, args.warmup, args.kernel_iters)
+    K, Np = r["K"], r["Np"]
     traffic = measured_traffic(args.form, K)
+    extra = {}
+    for name in [x for x in args.also.split(",") if x]:
+        if name in ("fp32", "bf16") and name != args.form:
+            o = time_single(dg, torch, m, N, name, args.steps, args.warmup, args.kernel_iters)
+            extra[name] = {"value": o["value"], "ms_per_step": o["ms"] / args.steps,
+                           "speedup_vs_headline": o["value"] / r["value"],
+                           "stage_kernel_ms": o["kernel_s"] * 1e3,
+                           "stage_GBs": o["achieved"], "frac": o["achieved"] / HBM_PEAK_GBS,
+                           "traffic": measured_traffic(name, K)}
+        elif name == "batch":
+            extra["batch"] = time_batch(dg, torch, args.batch_steps, 4, 10)
     if args.copy_mb:
         n = args.copy_mb * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(5):
             dst.copy_(src)
@@ -165,12 +240,12 @@ def main():
 
     out = {
         "metric": "DOF-stage updates/s",
-        "value": value,
+        "value": r["value"],
         "unit": "DOF-stage updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": r["ms"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -178,12 +253,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"trumpet-in-box, {K} tets, N={N} (Np={Np}), {args.form} form, "
                                "inflow pulse 0.1 p0, characteristic outflow, slip walls",
-                   "K": K, "N": N, "Np": Np, "dof": dof, "form": args.form,
-                   "t_end": t_end, "dt_last": dt_last, "wall_s": wall},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "stage_kernel<4,MODE_STAGE>", "kernel_ms": kernel_s * 1e3,
-                     "bytes_per_launch": nbytes},
+                   "K": K, "N": N, "Np": Np, "dof": r["dof"], "form": args.form,
+                   "t_end": r["t_end"], "dt_last": r["dt_last"], "wall_s": r["wall_s"],
+                   "blocks_per_cu": r["blocks_per_cu"]},
+        "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"stage_kernel<{N},MODE_STAGE>", "kernel_ms": r["kernel_s"] * 1e3,
+                     "bytes_per_launch": r["bytes"]},
+        "forms": extra,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

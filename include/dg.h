@@ -254,6 +254,21 @@ int dg_batch_set_launch(dg_batch* b, int blocks_per_cu, int waves_per_block);
  * fit); used by the autotuner. */
 int dg_set_launch(dg_ctx* ctx, int blocks_per_cu);
 
+/* ---- launch-shape autotuner -------------------------------------------------
+ * Times every launch shape of the stage kernel (resident blocks per CU; for
+ * batches also wavefronts per block) on the caller's stream with HIP events,
+ * applies the fastest and appends it to the text cache at cache_path (NULL or
+ * "" for no cache) under a key made of the workload sizes and the device
+ * architecture and CU count; a cached entry is applied without timing.
+ * Results of the solver do not depend on the launch shape.
+ * q is read and left unchanged; res is overwritten (scratch).  The chosen
+ * shape is returned through the optional out pointers.  Synchronizes. */
+int dg_autotune(dg_ctx* ctx, const float* q, float* res, const char* cache_path,
+                int* blocks_per_cu, void* stream);
+
+int dg_batch_autotune(dg_batch* b, float* const* q, float* const* res, const char* cache_path,
+                      int* blocks_per_cu, int* waves_per_block, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,4 +10,5 @@ from ._lib import (Context, DGError, EXPORTED, dg_mesh_setup, dg_destroy, dg_las
                    dg_sizes, dg_nodes, dg_reference_operators, dg_geometry, dg_rhs, dg_step,
                    dg_run, dg_stage, dg_last_step, dg_stable_dt, dg_prim_to_state, dg_state_to_prim,
                    dg_set_launch, Batch, MEMBERS, dg_batch_create, dg_batch_destroy,
-                   dg_batch_last_error, dg_batch_run, dg_batch_first_bad, dg_batch_set_launch)
+                   dg_batch_last_error, dg_batch_run, dg_batch_first_bad, dg_batch_set_launch,
+                   dg_autotune, dg_batch_autotune)

@@ -67,6 +67,10 @@ _SIGS = {
                                     _vp, _vp]),
     "dg_batch_first_bad": (ctypes.c_int, [_vp, _vp]),
     "dg_batch_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "dg_autotune": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int), _vp]),
+    "dg_batch_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                         ctypes.c_char_p, ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int), _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -353,3 +357,29 @@ def dg_batch_first_bad(b):
 
 def dg_batch_set_launch(b, blocks_per_cu, waves_per_block):
     _bcheck(_lib.dg_batch_set_launch(b.handle, int(blocks_per_cu), int(waves_per_block)), b)
+
+
+def dg_autotune(ctx, q, res, cache_path=None, stream=None):
+    """Pick the stage kernel's resident blocks per CU by timing; returns it."""
+    _check_state(ctx, q, "q")
+    _check_state(ctx, res, "res")
+    bpc = ctypes.c_int()
+    _check(_lib.dg_autotune(ctx.handle, _ptr(q), _ptr(res),
+                            cache_path.encode() if cache_path else None, ctypes.byref(bpc),
+                            _stream(stream)), ctx.handle)
+    return bpc.value
+
+
+def dg_batch_autotune(b, q, res, cache_path=None, stream=None):
+    """Pick the batched stage kernel's launch shape by timing; returns
+    (blocks_per_cu, waves_per_block)."""
+    ng = len(b.geoms)
+    for g, ctx in enumerate(b.geoms):
+        _check_batch_state(ctx, q[g], f"q[{g}]")
+        _check_batch_state(ctx, res[g], f"res[{g}]")
+    qp = (_vp * ng)(*[x.data_ptr() for x in q])
+    rp = (_vp * ng)(*[x.data_ptr() for x in res])
+    bpc, w = ctypes.c_int(), ctypes.c_int()
+    _bcheck(_lib.dg_batch_autotune(b.handle, qp, rp, cache_path.encode() if cache_path else None,
+                                   ctypes.byref(bpc), ctypes.byref(w), _stream(stream)), b)
+    return bpc.value, w.value

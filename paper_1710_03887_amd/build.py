@@ -11,7 +11,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["setup.cpp", "abi.cpp", "batch_abi.cpp", "kernels.hip", "batch.hip"]
+SOURCES = ["setup.cpp", "abi.cpp", "batch_abi.cpp", "autotune.cpp", "kernels.hip", "batch.hip"]
 LIB = os.path.join(HERE, "libdg.so")
 ARCH = os.environ.get("DG_OFFLOAD_ARCH", "gfx950")
 
@@ -27,6 +27,10 @@ def build(verbose=False):
     objs = []
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # FP32 division and square root from the hardware reciprocal and
+             # square-root instructions (1 ulp) instead of correctly rounded
+             # multi-instruction expansions
+             "-fno-hip-fp32-correctly-rounded-divide-sqrt",
              "-Wall", "-Wno-unused-function"]
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     for src in SOURCES:

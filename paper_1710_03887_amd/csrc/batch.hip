@@ -45,6 +45,23 @@ __device__ __forceinline__ T pick4b(const T* x, int f) {
   return f == 0 ? x[0] : f == 1 ? x[1] : f == 2 ? x[2] : x[3];
 }
 
+// Global-address-space views: loads through them are global (not flat)
+// loads, which the compiler does not count against LDS waits.
+typedef __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ const gfloat* gview(const float* p) { return (const gfloat*)(p); }
+__device__ __forceinline__ gfloat* gview(float* p) { return (gfloat*)(p); }
+
+// Read-only tables through the constant address space: wave-uniform
+// addresses become scalar loads.
+typedef __attribute__((address_space(4))) const double cdouble;
+typedef __attribute__((address_space(4))) const int cint;
+typedef __attribute__((address_space(4))) const uint8_t cbyte;
+typedef __attribute__((address_space(4))) const BatchGeom cgeom;
+
+__device__ __forceinline__ cgeom& geom(const BatchLaunch& L, int gi) {
+  return ((cgeom*)(L.geoms))[gi];
+}
+
 __device__ __forceinline__ float pulse(float amp, double alpha, double t) {
   const double T = 2.0 * M_PI / alpha;
   if (t >= 0.0 && t < T) return float(0.5 * amp * (1.0 - cos(alpha * t)));
@@ -53,7 +70,7 @@ __device__ __forceinline__ float pulse(float amp, double alpha, double t) {
 
 __device__ __forceinline__ int geom_of(const BatchLaunch& L, int64_t item) {
   int gi = 0;
-  while (gi + 1 < L.ngeom && item >= L.geoms[gi + 1].first) ++gi;
+  while (gi + 1 < L.ngeom && item >= geom(L, gi + 1).first) ++gi;
   return gi;
 }
 
@@ -66,7 +83,7 @@ __device__ __forceinline__ void flush_rate(const BatchLaunch& L, int gi, int lan
   bad |= __shfl_xor(bad, 32);
   const int e = lane & 15;
   if (lane < 16 && e < L.members) {
-    BatchScalars* sc = L.geoms[gi].sc;
+    BatchScalars* sc = geom(L, gi).sc;
     atomicMax(&sc->rate_bits[e], __float_as_uint(best));
     if (bad) atomicOr(&sc->bad[e], 1u);
   }
@@ -90,7 +107,8 @@ __global__ __launch_bounds__(64 * WAVES) void batch_stage_kernel(BatchLaunch L, 
   uint8_t* sNN = sFm + S::NF;
   uint8_t* sNF = sNN + 96 * Nfp;
   const Phys& P = L.phys;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int e = lane & 15, g = lane >> 4;
   const bool member = e < L.members;
 
@@ -107,37 +125,51 @@ __global__ __launch_bounds__(64 * WAVES) void batch_stage_kernel(BatchLaunch L, 
 
   float rate_best = 0.0f;
   unsigned rate_bad = 0u;
-  int rate_geom = -1;
+  int gi = -1;
+  int64_t first = 0, next_first = 0;
+  float dt = 0.0f, pin = 0.0f;
+  const gfloat* qi = nullptr;
+  gfloat* qo = nullptr;
+  gfloat* res = nullptr;
+  const cdouble* vgeo = nullptr;
+  const cdouble* sgeo = nullptr;
+  const cint* nbrs = nullptr;
+  const cbyte* finfo = nullptr;
 
   for (int64_t it = 0;; ++it) {
     const int64_t item = c0 + (int64_t(jb) + it * Gx) * WAVES + wave;
     if (item >= c1) break;
-    const int gi = geom_of(L, item);
-    if (rate_out && gi != rate_geom) {
-      if (rate_geom >= 0) flush_rate(L, rate_geom, lane, rate_best, rate_bad);
-      rate_geom = gi;
+    if (gi < 0 || item >= next_first) {   // items ascend: the geometry only advances
+      if (rate_out && gi >= 0) flush_rate(L, gi, lane, rate_best, rate_bad);
+      gi = __builtin_amdgcn_readfirstlane(geom_of(L, item));
+      cgeom& Gm = geom(L, gi);
+      const double tm = Gm.sc->t[e] + c_rk * Gm.sc->dt[e];
+      dt = float(Gm.sc->dt[e]);
+      pin = pulse(Gm.amp[e], P.alpha, tm);
+      qi = gview(Gm.q[parity]);
+      qo = gview(Gm.q[1 - parity]);
+      res = gview(Gm.res);
+      vgeo = (const cdouble*)Gm.vgeo;
+      sgeo = (const cdouble*)Gm.sgeo;
+      nbrs = (const cint*)Gm.nbr;
+      finfo = (const cbyte*)Gm.finfo;
+      first = Gm.first;
+      next_first = gi + 1 < L.ngeom ? geom(L, gi + 1).first : INT64_MAX;
     }
-    const BatchGeom& Gm = L.geoms[gi];
-    const int64_t k = item - Gm.first;
-    const float* qi = Gm.q[parity];
-    float* qo = Gm.q[1 - parity];
-    float* res = Gm.res;
-    const double tm = Gm.sc->t[e] + c_rk * Gm.sc->dt[e];
-    const float dt = float(Gm.sc->dt[e]);
-    const float pin = pulse(Gm.amp[e], P.alpha, tm);
+    const int64_t k = item - first;
 
     float gm[9], nx[4], ny[4], nz[4], fs[4];
     int nbr[4], finf[4];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) gm[i] = float(Gm.vgeo[k * 9 + i]);
+    for (int i = 0; i < 9; ++i) gm[i] = float(vgeo[k * 9 + i]);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      nx[f] = float(Gm.sgeo[k * 16 + f * 4 + 0]);
-      ny[f] = float(Gm.sgeo[k * 16 + f * 4 + 1]);
-      nz[f] = float(Gm.sgeo[k * 16 + f * 4 + 2]);
-      fs[f] = float(Gm.sgeo[k * 16 + f * 4 + 3]);
-      nbr[f] = Gm.nbr[k * 4 + f];
-      finf[f] = Gm.finfo[k * 4 + f];
+      nx[f] = float(sgeo[k * 16 + f * 4 + 0]);
+      ny[f] = float(sgeo[k * 16 + f * 4 + 1]);
+      nz[f] = float(sgeo[k * 16 + f * 4 + 2]);
+      fs[f] = float(sgeo[k * 16 + f * 4 + 3]);
+      nbr[f] = nbrs[k * 4 + f];
+      finf[f] = finfo[k * 4 + f];
     }
 
     // pass 1: Lax-Friedrichs speed per face and member
@@ -284,7 +316,7 @@ __global__ __launch_bounds__(64 * WAVES) void batch_stage_kernel(BatchLaunch L, 
         }
       }
   }
-  if (rate_out && rate_geom >= 0) flush_rate(L, rate_geom, lane, rate_best, rate_bad);
+  if (rate_out && gi >= 0) flush_rate(L, gi, lane, rate_best, rate_bad);
 }
 
 // CFL rate of the start state: max over face nodes of (N+1)^2/2 Fscale (|u|+c)
@@ -305,7 +337,7 @@ __global__ __launch_bounds__(256) void batch_rate_kernel(BatchLaunch L, int pari
       if (cur >= 0) flush_rate(L, cur, lane, best, bad);
       cur = gi;
     }
-    const BatchGeom& Gm = L.geoms[gi];
+    cgeom& Gm = geom(L, gi);
     const int64_t k = item - Gm.first;
     const float* qi = Gm.q[parity];
     for (int fq = 0; fq < S::NFQ; ++fq) {
@@ -334,7 +366,7 @@ __global__ __launch_bounds__(256) void batch_rate_kernel(BatchLaunch L, int pari
 __global__ void batch_finalize_kernel(BatchLaunch L) {
   const int gi = blockIdx.x, e = threadIdx.x;
   if (gi >= L.ngeom || e >= L.members) return;
-  BatchScalars* sc = L.geoms[gi].sc;
+  BatchScalars* sc = geom(L, gi).sc;
   const float rate = __uint_as_float(sc->rate_bits[e]);
   sc->dt[e] = rate > 0.0f ? sc->cfl / double(rate) : 0.0;
   if (sc->bad[e] && sc->first_bad[e] < 0) sc->first_bad[e] = sc->step;
@@ -345,7 +377,7 @@ __global__ void batch_finalize_kernel(BatchLaunch L) {
 __global__ void batch_advance_kernel(BatchLaunch L) {
   const int gi = blockIdx.x, e = threadIdx.x;
   if (gi >= L.ngeom || e >= L.members) return;
-  BatchScalars* sc = L.geoms[gi].sc;
+  BatchScalars* sc = geom(L, gi).sc;
   sc->t[e] += sc->dt[e];
   if (e == 0) sc->step += 1;
 }

@@ -12,25 +12,6 @@
 #include "batch.hpp"
 #include "ctx.hpp"
 
-
-struct dg_batch {
-  std::string err;
-  std::vector<dg_ctx*> geoms;
-  int members = dg::kMembers;
-  dg::BatchLaunch L;
-  std::vector<dg::BatchGeom> host_geoms;
-  dg::BatchGeom* dev_geoms = nullptr;
-  std::vector<dg::BatchScalars*> scal;     // device, one per geometry
-  std::vector<float*> partner;             // ping-pong partners, one per geometry
-  std::vector<dg::BatchScalars> host_scal;
-  uint8_t* node_faces = nullptr;
-  hipStream_t capture_stream = nullptr;
-  hipGraphExec_t graph = nullptr;
-  std::vector<float*> graph_q, graph_res;
-  int max_blocks_per_cu = 1;
-  std::vector<int64_t> first_bad;
-};
-
 namespace {
 
 int bfail(dg_batch* b, int code, const std::string& m) {

@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.hpp"
 #include "kernels.hpp"
 #include "setup.hpp"
 
@@ -51,4 +52,21 @@ struct dg_ctx {
   hipStream_t capture_stream = nullptr;
   dg::GraphCache two_steps;
   int64_t last_bad = -1;
+};
+
+struct dg_batch {
+  std::string err;
+  std::vector<dg_ctx*> geoms;
+  int members = dg::kMembers;
+  dg::BatchLaunch L;
+  std::vector<dg::BatchGeom> host_geoms;
+  dg::BatchGeom* dev_geoms = nullptr;
+  std::vector<dg::BatchScalars*> scal;     // device, one per geometry
+  std::vector<float*> partner;             // ping-pong partners, one per geometry
+  std::vector<dg::BatchScalars> host_scal;
+  uint8_t* node_faces = nullptr;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int max_blocks_per_cu = 1;
+  std::vector<int64_t> first_bad;
 };

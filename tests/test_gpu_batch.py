@@ -170,3 +170,34 @@ def test_batch_rejects_mismatched_contexts(setup):
         dg.dg_batch_create([pairs[0].ctx, other])
     with pytest.raises(dg.DGError):
         dg.dg_batch_create([pairs[0].ctx], members=17)
+
+
+def test_autotuners_keep_state_and_use_cache(setup, tmp_path):
+    pairs, starts = setup
+    cache = str(tmp_path / "tune.txt")
+    b = dg.dg_batch_create([p.ctx for p in pairs])
+    q = [_to_batch(p, s) for p, s in zip(pairs, starts)]
+    q_copy = [x.clone() for x in q]
+    res = [torch.zeros_like(x) for x in q]
+    shape = dg.dg_batch_autotune(b, q, res, cache)
+    assert shape[1] in (1, 2, 4, 8) and shape[0] >= 1
+    assert all(torch.equal(a, c) for a, c in zip(q, q_copy))
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("batch/N3/m16/K")
+    assert dg.dg_batch_autotune(b, q, res, cache) == shape      # from the cache
+    assert len(open(cache).read().splitlines()) == 1
+    # the tuned batch gives the untuned batch's results
+    t = dg.dg_batch_run(b, q, res, np.broadcast_to(AMPS, (3, 16)), 5, 0.5,
+                        np.full((3, 16), T_START))
+    torch.cuda.synchronize()
+    q_ref, t_ref, _ = _run_batch(pairs, starts, 5)
+    assert all(torch.equal(a, c) for a, c in zip(q, q_ref)) and np.array_equal(t, t_ref)
+
+    pair = pairs[0]
+    qd = pair.to_device(starts[0])
+    before = qd.clone()
+    r = torch.zeros_like(qd)
+    bpc = dg.dg_autotune(pair.ctx, qd, r, cache)
+    assert bpc >= 1 and torch.equal(qd, before)
+    assert dg.dg_autotune(pair.ctx, qd, r, cache) == bpc
+    assert len(open(cache).read().splitlines()) == 2
