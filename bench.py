@@ -40,8 +40,8 @@ def stage_bytes(K, Np, reads_res=True):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("kernels.hip", "physics.hpp", "kernels.hpp"):
-        with open(os.path.join(ROOT, "paper_1710_03887_amd", "csrc", name), "rb") as f:
+    for name in ("csrc/kernels.hip", "csrc/physics.hpp", "csrc/kernels.hpp", "build.py"):
+        with open(os.path.join(ROOT, "paper_1710_03887_amd", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
