@@ -258,6 +258,8 @@ def main():
                    "blocks_per_cu": r["blocks_per_cu"]},
         "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
+                                     "copy-calibrated)",
                      "kernel": f"stage_kernel<{N},MODE_STAGE>", "kernel_ms": r["kernel_s"] * 1e3,
                      "bytes_per_launch": r["bytes"]},
         "forms": extra,
