@@ -183,7 +183,16 @@ def trumpet_domain(kind="box", target_K=200_000, scale=1.0, wall_tag=BC_WALL,
     nt, nr1, nr2, xs = layout(s)
     if kind == "half":
         xs = xs[xs >= 0.0]
-    desc, per, quads = _o_grid(nt, nr1, nr2)
+    return _assemble(kind, nt, nr1, nr2, xs, x_lo, x_hi, half_w, sph_c, sph_r, wall_tag,
+                     inflow_tag, outer_tag, return_info, scale)
+
+
+def _assemble(kind, nt, nr1, nr2, xs, x_lo, x_hi, half_w, sph_c, sph_r, wall_tag, inflow_tag,
+              outer_tag, return_info, scale, ext_rings=None):
+    """Tetrahedra of the extruded O-grid.  `ext_rings` (box only) appends
+    rings beyond the outer square: a list of half-widths > half_w."""
+    n_ext = 0 if ext_rings is None else len(ext_rings)
+    desc, per, quads = _o_grid(nt, nr1, nr2 + n_ext)
     nodes2 = len(desc)
     nr = nr1 + nr2
     perim = _perimeter_points(nt)
@@ -213,6 +222,8 @@ def trumpet_domain(kind="box", target_K=200_000, scale=1.0, wall_tag=BC_WALL,
             if r <= nr1:
                 w = r / nr1
                 Y[ix, n] = (1 - w) * alpha * R * S + w * C
+            elif r > nr:
+                Y[ix, n] = ext_rings[r - nr - 1] * S
             else:
                 if kind == "sphere":
                     O = outer_r * S / np.linalg.norm(S)
@@ -294,3 +305,57 @@ def _sphere_planes(xs, x_lo, x_hi, c, r):
     cs = np.sqrt(np.maximum(r ** 2 - (xs - c[0]) ** 2, 0.0))
     keep = cs > 1.6 * _contour_radius(xs, x_lo, x_hi)
     return xs[keep]
+
+
+def _growing_cells(a, b, h0, growth):
+    """Planes from a to b (either direction) whose cells start near h0 and
+    grow by `growth` per cell, rescaled to end exactly at b."""
+    L = abs(b - a)
+    h, tot, cells = h0 * growth, 0.0, []
+    while tot + h < L:
+        cells.append(h)
+        tot += h
+        h *= growth
+    cells.append(max(L - tot, 0.5 * cells[-1] if cells else L))
+    w = np.array(cells) * (L / np.sum(cells))
+    return a + np.sign(b - a) * np.concatenate([[0.0], np.cumsum(w)])
+
+
+def trumpet_nested(target_K=50_000, scale=3.0, growth=1.25):
+    """The trumpet in the box domain (about target_K tetrahedra) and the same
+    scene in an outer box `scale` times larger about (0.65, 0, 0) that
+    contains the smaller mesh element for element (same vertices in the same
+    local order), so that solutions compare node by node.
+
+    Beyond the small box, x-planes and square rings are added with cells
+    growing geometrically by `growth` from the small box's outermost cells.
+    Returns (big, small, emap): emap[k] is the big-mesh element of small-mesh
+    element k.
+    """
+    small = trumpet_domain("box", target_K, return_info=True)
+    info = small["info"]
+    nt, nr1, nr2, xs = info["nt"], info["nr1"], info["nr2"], info["x_planes"]
+    x_lo, x_hi, half_w = -0.5, 1.8, 1.0
+    X_lo = CENTER_X + (x_lo - CENTER_X) * scale
+    X_hi = CENTER_X + (x_hi - CENTER_X) * scale
+    H = half_w * scale
+    back = _growing_cells(x_lo, X_lo, xs[1] - xs[0], growth)[1:][::-1]
+    front = _growing_cells(x_hi, X_hi, xs[-1] - xs[-2], growth)[1:]
+    xs_big = np.concatenate([back, xs, front])
+    rings = _growing_cells(half_w, H, xs[-1] - xs[-2], growth)[1:]
+    big = _assemble("box", nt, nr1, nr2, xs_big, x_lo, x_hi, half_w, None, None, BC_WALL,
+                    BC_INFLOW, BC_OUTFLOW_CHAR, False, scale, ext_rings=list(rings))
+    # element map by vertex coordinates
+    def keys(m):
+        return np.round(m["xyz"].reshape(len(m["xyz"]), 12), 9)
+    ks, kb = keys(small), keys(big)
+    allk = np.concatenate([ks, kb])
+    _, inv = np.unique(allk, axis=0, return_inverse=True)
+    inv = inv.ravel()
+    pos = np.full(inv.max() + 1, -1, dtype=np.int64)
+    pos[inv[len(ks):]] = np.arange(len(kb))
+    emap = pos[inv[:len(ks)]]
+    if np.any(emap < 0):
+        raise RuntimeError("small mesh is not nested in the big mesh")
+    small.pop("info")
+    return big, small, emap
