@@ -191,6 +191,15 @@ int dg_stage(dg_ctx* ctx, const float* q_in, float* q_out, float* res, double a,
 int dg_run(dg_ctx* ctx, float* q, float* res, int64_t nsteps, double cfl,
            double* t_inout, double* dt_last, void* stream);
 
+/*
+ * dg_run with a fixed time step: every step takes dt (> 0) instead of the
+ * CFL rule, so that runs on different meshes advance in lockstep (used to
+ * compare a truncated domain against a larger one).  Same ownership,
+ * synchronization and errors as dg_run.
+ */
+int dg_run_fixed(dg_ctx* ctx, float* q, float* res, int64_t nsteps, double dt, double* t_inout,
+                 void* stream);
+
 /* Step index (0-based, within the last dg_run) of the first non-physical
  * state, or -1. */
 int64_t dg_last_step(const dg_ctx* ctx);
@@ -268,6 +277,71 @@ int dg_autotune(dg_ctx* ctx, const float* q, float* res, const char* cache_path,
 
 int dg_batch_autotune(dg_batch* b, float* const* q, float* const* res, const char* cache_path,
                       int* blocks_per_cu, int* waves_per_block, void* stream);
+
+/* ---- learned boundary closure ------------------------------------------------
+ * A multilayer perceptron 78 -> 128 -> 128 -> 75 with GELU activations maps a
+ * boundary face's interior trace -- the perturbation q - q0 of the five
+ * conserved variables at its 15 face nodes (N = 4), variable-major
+ * x[v * 15 + i], divided by a normalization amplitude -- followed by the
+ * face's outward unit normal, to the exterior trace in the same units.  It
+ * stands in for the ghost state of the boundary conditions of Section 2
+ * (faces tagged DG_BC_LEARNED), with the characteristic ghost as fallback.
+ * Parameters: one FP32 vector of DG_MLP_PARAMS values, W1 [128][78], b1,
+ * W2 [128][128], b2, W3 [75][128], b3 (row-major, out x in).
+ * Training: FP32, loss = mean over rows of |y_hat - y|^2 / (|y|^2 + 1e-6),
+ * Adam (beta 0.9, 0.999, eps 1e-8).  Inference in the solver: BF16 weights
+ * and activations with FP32 accumulation.
+ */
+#define DG_MLP_PARAMS 36299
+typedef struct dg_mlp dg_mlp;
+
+/* params: host FP32 [DG_MLP_PARAMS], copied.  Synchronizes. */
+int dg_mlp_create(const float* params, void* stream, dg_mlp** out);
+int dg_mlp_destroy(dg_mlp* m);
+const char* dg_mlp_last_error(const dg_mlp* m);
+/* host FP32 [DG_MLP_PARAMS]; synchronize */
+int dg_mlp_get_params(dg_mlp* m, float* params, void* stream);
+int dg_mlp_set_params(dg_mlp* m, const float* params, void* stream);
+
+/* Y [B][75] = network(X [B][78]); device pointers; bf16 != 0 selects the
+ * BF16 inference kernel, else FP32.  Asynchronous (FP32 may allocate its
+ * workspace the first time a larger B is seen). */
+int dg_mlp_infer(dg_mlp* m, const float* X, float* Y, int64_t B, int bf16, void* stream);
+
+/* Loss and gradient for rows (X [B][78], Y [B][75]) (device): grads is a
+ * device FP32 [DG_MLP_PARAMS] (NULL: internal); *loss (host, optional) is
+ * read back with a synchronization.  Deterministic. */
+int dg_mlp_grad(dg_mlp* m, const float* X, const float* Y, int64_t B, float* loss, float* grads,
+                void* stream);
+
+/* One Adam step on the minibatch rows[0..B) of the device data set
+ * (X [n_rows][78], Y [n_rows][75]); rows is a device int64 array (indices
+ * are clamped to the set), or NULL for the first B rows.  lr: step size.
+ * *loss (host, optional) gets the minibatch loss before the update and
+ * synchronizes. */
+int dg_mlp_train_step(dg_mlp* m, const float* X, const float* Y, int64_t n_rows,
+                      const int64_t* rows, int64_t B, float lr, float* loss, void* stream);
+
+/* Attach (m != NULL) or detach (m == NULL) a network to the context's faces
+ * tagged DG_BC_LEARNED (N = 4 only).  norm: the trace normalization; the
+ * network's ghost is used on a face when the largest |p'| of its interior
+ * trace lies in [p_lo, p_hi] and the ghost has rho > 0 and p > 0 at every
+ * node, else the characteristic ghost.  The network is borrowed and must
+ * outlive the attachment; weight updates take effect at the next launch. */
+int dg_set_learned_bc(dg_ctx* ctx, dg_mlp* m, double norm, double p_lo, double p_hi);
+
+/* Number of faces tagged DG_BC_LEARNED; when faces is not NULL, writes their
+ * k * 4 + f (host int64) in the order the solver indexes them. */
+int64_t dg_learned_faces(const dg_ctx* ctx, int64_t* faces);
+
+/* Network rows from a state: for faces[j] = k * 4 + f (device int64 [nf]),
+ * X[j] (device FP32 [nf][78]) = interior trace / norm and normal, and when Y
+ * is not NULL, Y[j] (device [nf][75]) = exterior trace / norm: the
+ * neighbour's trace on interior faces (a larger domain's solution), the ghost
+ * of the face's tag on boundary faces.  Face indices outside the mesh are
+ * skipped.  Asynchronous. */
+int dg_sample_traces(dg_ctx* ctx, const float* q, const int64_t* faces, int64_t nf, double norm,
+                     float* X, float* Y, void* stream);
 
 #ifdef __cplusplus
 }

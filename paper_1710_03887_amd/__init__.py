@@ -11,4 +11,7 @@ from ._lib import (Context, DGError, EXPORTED, dg_mesh_setup, dg_destroy, dg_las
                    dg_run, dg_stage, dg_last_step, dg_stable_dt, dg_prim_to_state, dg_state_to_prim,
                    dg_set_launch, Batch, MEMBERS, dg_batch_create, dg_batch_destroy,
                    dg_batch_last_error, dg_batch_run, dg_batch_first_bad, dg_batch_set_launch,
-                   dg_autotune, dg_batch_autotune)
+                   dg_autotune, dg_batch_autotune, dg_run_fixed, Mlp, DG_MLP_PARAMS,
+                   dg_mlp_create, dg_mlp_destroy, dg_mlp_last_error, dg_mlp_get_params,
+                   dg_mlp_set_params, dg_mlp_infer, dg_mlp_grad, dg_mlp_train_step,
+                   dg_set_learned_bc, dg_learned_faces, dg_sample_traces)

@@ -71,6 +71,19 @@ _SIGS = {
     "dg_batch_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                          ctypes.c_char_p, ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int), _vp]),
+    "dg_run_fixed": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, ctypes.POINTER(_f64), _vp]),
+    "dg_mlp_create": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),
+    "dg_mlp_destroy": (ctypes.c_int, [_vp]),
+    "dg_mlp_last_error": (ctypes.c_char_p, [_vp]),
+    "dg_mlp_get_params": (ctypes.c_int, [_vp, _vp, _vp]),
+    "dg_mlp_set_params": (ctypes.c_int, [_vp, _vp, _vp]),
+    "dg_mlp_infer": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int, _vp]),
+    "dg_mlp_grad": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(ctypes.c_float), _vp, _vp]),
+    "dg_mlp_train_step": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, ctypes.c_float,
+                                         ctypes.POINTER(ctypes.c_float), _vp]),
+    "dg_set_learned_bc": (ctypes.c_int, [_vp, _vp, _f64, _f64, _f64]),
+    "dg_learned_faces": (_i64, [_vp, _vp]),
+    "dg_sample_traces": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, _vp, _vp, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -383,3 +396,147 @@ def dg_batch_autotune(b, q, res, cache_path=None, stream=None):
     _bcheck(_lib.dg_batch_autotune(b.handle, qp, rp, cache_path.encode() if cache_path else None,
                                    ctypes.byref(bpc), ctypes.byref(w), _stream(stream)), b)
     return bpc.value, w.value
+
+
+def dg_run_fixed(ctx, q, res, nsteps, dt, t=0.0, stream=None):
+    """dg_run with a fixed time step dt; returns the end time."""
+    _check_state(ctx, q, "q")
+    _check_state(ctx, res, "res")
+    tt = _f64(t)
+    _check(_lib.dg_run_fixed(ctx.handle, _ptr(q), _ptr(res), int(nsteps), float(dt),
+                             ctypes.byref(tt), _stream(stream)), ctx.handle)
+    return tt.value
+
+
+# ---- learned boundary closure ------------------------------------------------------
+DG_MLP_PARAMS = 36299
+MLP_IN, MLP_OUT = 78, 75
+
+
+class Mlp:
+    """Owns a dg_mlp handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            _lib.dg_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _mcheck(code, m):
+    if code != DG_OK:
+        msg = _lib.dg_mlp_last_error(m.handle if m is not None else None)
+        raise DGError(code, msg.decode() if msg else "")
+
+
+def _check_dev(x, shape, dtype, name):
+    if tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(x.shape)}, expected {tuple(shape)}")
+    if str(x.dtype) != dtype or not x.is_cuda or not x.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor")
+
+
+def dg_mlp_create(params, stream=None):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.shape != (DG_MLP_PARAMS,):
+        raise ValueError(f"params must have {DG_MLP_PARAMS} values")
+    h = _vp()
+    code = _lib.dg_mlp_create(p.ctypes.data, _stream(stream), ctypes.byref(h))
+    if code != DG_OK:
+        raise DGError(code, "dg_mlp_create")
+    return Mlp(h)
+
+
+def dg_mlp_destroy(m):
+    m.close()
+
+
+def dg_mlp_last_error(m):
+    msg = _lib.dg_mlp_last_error(m.handle)
+    return msg.decode() if msg else ""
+
+
+def dg_mlp_get_params(m, stream=None):
+    out = np.empty(DG_MLP_PARAMS, dtype=np.float32)
+    _mcheck(_lib.dg_mlp_get_params(m.handle, out.ctypes.data, _stream(stream)), m)
+    return out
+
+
+def dg_mlp_set_params(m, params, stream=None):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.shape != (DG_MLP_PARAMS,):
+        raise ValueError(f"params must have {DG_MLP_PARAMS} values")
+    _mcheck(_lib.dg_mlp_set_params(m.handle, p.ctypes.data, _stream(stream)), m)
+
+
+def dg_mlp_infer(m, X, Y, bf16=True, stream=None):
+    B = X.shape[0]
+    _check_dev(X, (B, MLP_IN), "torch.float32", "X")
+    _check_dev(Y, (B, MLP_OUT), "torch.float32", "Y")
+    _mcheck(_lib.dg_mlp_infer(m.handle, _ptr(X), _ptr(Y), B, 1 if bf16 else 0, _stream(stream)), m)
+
+
+def dg_mlp_grad(m, X, Y, grads=None, stream=None):
+    """Returns (loss, grads) with grads a device FP32 tensor."""
+    import torch
+    B = X.shape[0]
+    _check_dev(X, (B, MLP_IN), "torch.float32", "X")
+    _check_dev(Y, (B, MLP_OUT), "torch.float32", "Y")
+    if grads is None:
+        grads = torch.empty(DG_MLP_PARAMS, dtype=torch.float32, device=X.device)
+    _check_dev(grads, (DG_MLP_PARAMS,), "torch.float32", "grads")
+    loss = ctypes.c_float()
+    _mcheck(_lib.dg_mlp_grad(m.handle, _ptr(X), _ptr(Y), B, ctypes.byref(loss), _ptr(grads),
+                             _stream(stream)), m)
+    return loss.value, grads
+
+
+def dg_mlp_train_step(m, X, Y, lr, rows=None, batch=None, want_loss=True, stream=None):
+    """One Adam step on rows `rows` (device int64) of the data set (X, Y),
+    or on its first `batch` rows.  Returns the minibatch loss (or None)."""
+    n = X.shape[0]
+    _check_dev(X, (n, MLP_IN), "torch.float32", "X")
+    _check_dev(Y, (n, MLP_OUT), "torch.float32", "Y")
+    if rows is not None:
+        _check_dev(rows, (rows.shape[0],), "torch.int64", "rows")
+        B = rows.shape[0]
+    else:
+        B = n if batch is None else int(batch)
+    loss = ctypes.c_float()
+    _mcheck(_lib.dg_mlp_train_step(m.handle, _ptr(X), _ptr(Y), n, _ptr(rows), B, float(lr),
+                                   ctypes.byref(loss) if want_loss else None, _stream(stream)), m)
+    return loss.value if want_loss else None
+
+
+def dg_set_learned_bc(ctx, m, norm, p_lo, p_hi):
+    _check(_lib.dg_set_learned_bc(ctx.handle, m.handle if m is not None else None, float(norm),
+                                  float(p_lo), float(p_hi)), ctx.handle)
+    ctx.mlp = m          # keep the network alive while attached
+
+
+def dg_learned_faces(ctx):
+    n = _lib.dg_learned_faces(ctx.handle, None)
+    out = np.empty(max(n, 0), dtype=np.int64)
+    if n > 0:
+        _lib.dg_learned_faces(ctx.handle, out.ctypes.data)
+    return out
+
+
+def dg_sample_traces(ctx, q, faces, norm, X, Y=None, stream=None):
+    _check_state(ctx, q, "q")
+    nf = faces.shape[0]
+    _check_dev(faces, (nf,), "torch.int64", "faces")
+    nfp = ctx.Nfp
+    _check_dev(X, (nf, 5 * nfp + 3), "torch.float32", "X")
+    if Y is not None:
+        _check_dev(Y, (nf, 5 * nfp), "torch.float32", "Y")
+    _check(_lib.dg_sample_traces(ctx.handle, _ptr(q), _ptr(faces), nf, float(norm), _ptr(X),
+                                 _ptr(Y), _stream(stream)), ctx.handle)

@@ -76,8 +76,16 @@ int build_device(dg_ctx* c, hipStream_t s) {
     }
   std::vector<int32_t> nbr(size_t(K) * 4);
   std::vector<uint8_t> finfo(size_t(K) * 4);
+  c->lface_host.clear();
   for (size_t i = 0; i < nbr.size(); ++i) {
-    nbr[i] = mh.EToE[i] >= 0 ? mh.EToE[i] : -int32_t(mh.bc[i]);
+    if (mh.EToE[i] >= 0) {
+      nbr[i] = mh.EToE[i];
+    } else if (mh.bc[i] == DG_BC_LEARNED) {   // -(tag + 8 * index of the learned face)
+      nbr[i] = -int32_t(DG_BC_LEARNED + 8 * c->lface_host.size());
+      c->lface_host.push_back(int32_t(i));
+    } else {
+      nbr[i] = -int32_t(mh.bc[i]);
+    }
     finfo[i] = uint8_t(mh.EToF[i] | (mh.orient[i] << 2));
   }
 
@@ -112,6 +120,16 @@ int build_device(dg_ctx* c, hipStream_t s) {
   if ((rc = upload(c, nbr.data(), nbr.size(), &dN, s))) return rc;
   if ((rc = upload(c, finfo.data(), finfo.size(), &dFi, s))) return rc;
   if ((rc = upload<float>(c, nullptr, size_t(K) * 5 * Np, &c->qbuf, s))) return rc;
+  if (!c->lface_host.empty()) {
+    int32_t* dLf;
+    float* dGh;
+    const int64_t nl = int64_t(c->lface_host.size());
+    if ((rc = upload(c, c->lface_host.data(), c->lface_host.size(), &dLf, s))) return rc;
+    if ((rc = upload<float>(c, nullptr, size_t(nl) * 5 * Np, &dGh, s))) return rc;
+    c->lbc.lface = dLf;
+    c->lbc.ghost = dGh;
+    c->lbc.nl = nl;
+  }
   if ((rc = upload<dg::RunScalars>(c, nullptr, 1, &c->run, s))) return rc;
   c->host_run = dg::RunScalars{};
   c->host_run.first_bad = -1;
@@ -130,6 +148,19 @@ int build_device(dg_ctx* c, hipStream_t s) {
   return DG_OK;
 }
 
+// One stage launch, preceded by the learned ghost traces of q_in when a
+// network is attached.
+hipError_t stage(dg_ctx* c, int mode, const float* q_in, float* q_out, float* res, float* out,
+                 float a, float b, double cc, double t, double dt, dg::RunScalars* run,
+                 int rate_out, hipStream_t s) {
+  if (c->mlp) {
+    hipError_t e = dg::mlp_sync_bf16(c->mlp, s);
+    if (e == hipSuccess) e = dg::launch_learned_ghost(c->dm, c->lbc, q_in, s);
+    if (e != hipSuccess) return e;
+  }
+  return dg::launch_stage(c->dm, mode, q_in, q_out, res, out, a, b, cc, t, dt, run, rate_out, s);
+}
+
 // Enqueue one LSERK step on `s` with state ping-ponging between q and the
 // context buffer; returns with the state in q when `end_in_q`, which needs
 // an even number of stage swaps in total (handled by the caller).
@@ -139,7 +170,7 @@ hipError_t enqueue_stages(dg_ctx* c, float* q, float* res, bool start_in_q, doub
   int cur = start_in_q ? 0 : 1;
   for (int i = 0; i < 5; ++i) {
     // the last stage of a run step also reduces the next step's CFL rate
-    hipError_t e = dg::launch_stage(c->dm, dg::MODE_STAGE, bufs[cur], bufs[1 - cur], res, nullptr,
+    hipError_t e = stage(c, dg::MODE_STAGE, bufs[cur], bufs[1 - cur], res, nullptr,
                                     float(dg::kRK4a[i]), float(dg::kRK4b[i]), dg::kRK4c[i], t, dt, run,
                                     i == 4 ? 1 : 0, s);
     if (e != hipSuccess) return e;
@@ -263,7 +294,7 @@ int dg_rhs(dg_ctx* c, const float* q, float* rhs, double t, void* stream) {
   int rc = need_device(c);
   if (rc) return rc;
   if (!q || !rhs) return fail(c, DG_EINVAL, "null state pointer");
-  hipError_t e = dg::launch_stage(c->dm, dg::MODE_RHS, q, nullptr, nullptr, rhs, 0.f, 0.f, 0.0, t,
+  hipError_t e = stage(c, dg::MODE_RHS, q, nullptr, nullptr, rhs, 0.f, 0.f, 0.0, t,
                                   0.0, nullptr, 0, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? DG_OK : hip_fail(c, e, "stage launch");
 }
@@ -287,7 +318,7 @@ int dg_stage(dg_ctx* c, const float* q_in, float* q_out, float* res, double a, d
   if (rc) return rc;
   if (!q_in || !q_out || !res) return fail(c, DG_EINVAL, "null state pointer");
   if (q_in == q_out) return fail(c, DG_EINVAL, "q_in and q_out must differ");
-  hipError_t e = dg::launch_stage(c->dm, dg::MODE_STAGE, q_in, q_out, res, nullptr, float(a),
+  hipError_t e = stage(c, dg::MODE_STAGE, q_in, q_out, res, nullptr, float(a),
                                   float(b), 0.0, t_stage, dt, nullptr, 0,
                                   static_cast<hipStream_t>(stream));
   return e == hipSuccess ? DG_OK : hip_fail(c, e, "stage launch");
@@ -314,17 +345,19 @@ int dg_stable_dt(dg_ctx* c, const float* q, double cfl, double* dt, void* stream
   return DG_OK;
 }
 
-int dg_run(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double* t_inout,
-           double* dt_last, void* stream) {
-  int rc = need_device(c);
-  if (rc) return rc;
-  if (!q || !res || !t_inout) return fail(c, DG_EINVAL, "null argument");
-  if (nsteps < 0 || !(cfl > 0.0)) return fail(c, DG_EINVAL, "need nsteps >= 0 and cfl > 0");
-  hipStream_t s = static_cast<hipStream_t>(stream);
+namespace {
+
+int run_impl(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double fixed_dt,
+             double* t_inout, double* dt_last, hipStream_t s) {
   c->host_run = dg::RunScalars{};
   c->host_run.t = *t_inout;
   c->host_run.cfl = cfl;
+  c->host_run.fixed_dt = fixed_dt;
   c->host_run.first_bad = -1;
+  if (c->mlp) {
+    const hipError_t e = dg::mlp_sync_bf16(c->mlp, s);
+    if (e != hipSuccess) return hip_fail(c, e, "learned closure weights");
+  }
   hipError_t e = hipMemcpyAsync(c->run, &c->host_run, sizeof(dg::RunScalars),
                                 hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
@@ -383,6 +416,26 @@ int dg_run(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double* 
   c->last_bad = c->host_run.first_bad;
   if (c->last_bad >= 0) return fail(c, DG_ENONPHYS, "non-physical state during dg_run");
   return DG_OK;
+}
+
+}  // namespace
+
+int dg_run(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double* t_inout,
+           double* dt_last, void* stream) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (!q || !res || !t_inout) return fail(c, DG_EINVAL, "null argument");
+  if (nsteps < 0 || !(cfl > 0.0)) return fail(c, DG_EINVAL, "need nsteps >= 0 and cfl > 0");
+  return run_impl(c, q, res, nsteps, cfl, 0.0, t_inout, dt_last, static_cast<hipStream_t>(stream));
+}
+
+int dg_run_fixed(dg_ctx* c, float* q, float* res, int64_t nsteps, double dt, double* t_inout,
+                 void* stream) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (!q || !res || !t_inout) return fail(c, DG_EINVAL, "null argument");
+  if (nsteps < 0 || !(dt > 0.0)) return fail(c, DG_EINVAL, "need nsteps >= 0 and dt > 0");
+  return run_impl(c, q, res, nsteps, 1.0, dt, t_inout, nullptr, static_cast<hipStream_t>(stream));
 }
 
 int64_t dg_last_step(const dg_ctx* c) { return c ? c->last_bad : -1; }

@@ -10,6 +10,7 @@
 
 #include "batch.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
 #include "setup.hpp"
 
 namespace dg {
@@ -38,8 +39,13 @@ struct GraphCache {
 
 }  // namespace dg
 
+struct dg_mlp;
+
 struct dg_ctx {
   std::string err;
+  dg_mlp* mlp = nullptr;            // attached learned closure, or null
+  dg::LearnedBC lbc;                // its device tables (lface, ghost) and window
+  std::vector<int32_t> lface_host;  // learned faces k * 4 + f, in nbr-index order
   int max_blocks_per_cu = 1;        // occupancy limit of the stage kernel
   bool host_only = false;
   dg::RefOps ops;
@@ -70,3 +76,21 @@ struct dg_batch {
   int max_blocks_per_cu = 1;
   std::vector<int64_t> first_bad;
 };
+
+struct dg_mlp {
+  std::string err;
+  float* P = nullptr;        // parameters [kMlpParams]
+  float* grads = nullptr;
+  float* m = nullptr;        // Adam moments
+  float* v = nullptr;
+  uint16_t* Wb = nullptr;    // BF16 weights (padded layout)
+  float* loss_dev = nullptr;
+  int64_t t = 0;             // Adam steps taken
+  bool bf16_stale = true;
+  dg::MlpWork w;
+};
+
+namespace dg {
+// Brings the BF16 weights of `m` up to date on stream s.
+hipError_t mlp_sync_bf16(dg_mlp* m, hipStream_t s);
+}  // namespace dg

@@ -190,6 +190,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       if (ok && fq < S::NFQ && nb >= 0) {
         const int inf = (fiN >> (8 * f)) & 0xff;
         off = nb * ST + sNN[((f * 4 + (inf & 3)) * 6 + (inf >> 2)) * Nfp + ii];
+      } else if (ok && fq < S::NFQ && m.lghost && ((-nb) & 7) == BC_LEARNED) {
+        off = -2 - (((-nb) >> 3) * ST + ii);  // learned ghost trace, same layout
       }
       goff[kq] = off;
     }
@@ -212,8 +214,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
     for (int kq = 0; kq < kFQ; ++kq) {
       const int fq = w + kWaves * kq;
-      if (goff[kq] >= 0) {
-        const float* src = q_in + goff[kq];
+      if (goff[kq] != -1) {
+        const float* src = goff[kq] >= 0 ? q_in + goff[kq] : m.lghost + (-2 - goff[kq]);
 #pragma unroll
         for (int v = 0; v < 5; ++v)
           __builtin_amdgcn_global_load_lds((void*)(src + v * Np), (lds_ptr_t)(sP + (fq * 5 + v) * 64),
@@ -286,7 +288,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       primitive<MOVING>(P, qm, wm);
       const int nb = valid ? pick4(nbr, f) : -BC_PASSTHRU;
       float* slot = sP + fq * 5 * 64 + lane;
-      if (nb >= 0) {
+      if (nb >= 0 || (m.lghost && ((-nb) & 7) == BC_LEARNED)) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) qp[v] = slot[v * 64];
       } else {
@@ -583,7 +585,7 @@ __global__ __launch_bounds__(256) void rate_kernel(DeviceMesh m, const float* __
 
 __global__ void finalize_kernel(RunScalars* run) {
   const float rate = __uint_as_float(run->rate_bits);
-  run->dt = (rate > 0.0f) ? run->cfl / double(rate) : 0.0;
+  run->dt = run->fixed_dt > 0.0 ? run->fixed_dt : (rate > 0.0f) ? run->cfl / double(rate) : 0.0;
   if (run->bad && run->first_bad < 0) run->first_bad = run->step;
   run->rate_bits = 0u;
   run->bad = 0u;

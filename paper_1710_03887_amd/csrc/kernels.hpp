@@ -25,6 +25,9 @@ struct DeviceMesh {
   const double* sgeo = nullptr;     // [K][4][4] nx ny nz Fscale
   const int32_t* nbr = nullptr;     // [K][4] neighbour element, or -tag
   const uint8_t* finfo = nullptr;   // [K][4] neighbour face | orientation << 2
+  // learned ghost traces [n_learned][5][Np] (nodes 0..Nfp-1), or null; a
+  // learned face's nbr entry is -(BC_LEARNED + 8 * its index)
+  const float* lghost = nullptr;
   Phys phys;
 };
 
@@ -33,7 +36,7 @@ struct RunScalars {
   double t;
   double dt;
   double cfl;
-  double pad0;
+  double fixed_dt;   // > 0: every step takes this dt instead of the CFL rule
   int64_t step;
   int64_t first_bad;
   uint32_t rate_bits;

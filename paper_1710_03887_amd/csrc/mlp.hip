@@ -1,0 +1,560 @@
+// Learned boundary closure kernels (gfx950): FP32 training on MFMA f32
+// 16x16x4, BF16 inference on MFMA bf16 16x16x32, the per-stage learned ghost
+// traces and the trace sampler.  Every reduction has a fixed order, so
+// results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "mlp.hpp"
+#include "physics.hpp"
+
+namespace dg {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
+         x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+__device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
+
+// ---- FP32 GEMM with split-K over the four wavefronts of a block ------------
+
+enum : int { EP_STORE = 0, EP_BIAS = 1, EP_BIAS_GELU = 2, EP_GELU_GRAD = 3, EP_WGRAD = 4 };
+
+// C (M x N) = sum_k A(m, k) B(k, n) with A(m, k) = A[m sam + k sak] and
+// B(k, n) = B[k sbk + n sbn].  Epilogues:
+//   EP_STORE      C = AB
+//   EP_BIAS       C = AB + bias[n]
+//   EP_BIAS_GELU  C = AB + bias[n] (pre-activation), C2 = gelu(C)
+//   EP_GELU_GRAD  C = AB * gelu'(Z)   (Z in C's layout)
+//   EP_WGRAD      C = AB and C2[m] = sum_k A(m, k) (bias gradient: a column
+//                 of ones appended to B)
+struct Gemm {
+  int M, N, K;
+  const float* A;
+  int64_t sam, sak;
+  const float* B;
+  int64_t sbk, sbn;
+  float* C;
+  int64_t ldc;
+  const float* bias;
+  float* C2;
+  const float* Z;
+};
+
+template <int EP>
+__global__ __launch_bounds__(256) void gemm_kernel(Gemm g) {
+  __shared__ floatx4 red[4][64];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, e = lane & 15, q4 = lane >> 4;
+  const int m0 = blockIdx.x * 16, n0 = blockIdx.y * 16;
+  const int m = m0 + e, n = n0 + e;
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+  for (int k0 = 4 * w; k0 < g.K; k0 += 16) {
+    const int k = k0 + q4;
+    const bool kin = k < g.K;
+    const float a = (kin && m < g.M) ? g.A[int64_t(m) * g.sam + int64_t(k) * g.sak] : 0.0f;
+    float b = 0.0f;
+    if (kin) {
+      if (EP == EP_WGRAD && n == g.N) b = 1.0f;
+      else if (n < g.N) b = g.B[int64_t(k) * g.sbk + int64_t(n) * g.sbn];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w != 0) return;
+  const floatx4 s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int mm = m0 + 4 * q4 + r;
+    if (mm >= g.M) continue;
+    float v = s[r];
+    if (EP == EP_WGRAD) {
+      if (n < g.N) g.C[int64_t(mm) * g.ldc + n] = v;
+      else if (n == g.N) g.C2[mm] = v;
+      continue;
+    }
+    if (n >= g.N) continue;
+    const int64_t o = int64_t(mm) * g.ldc + n;
+    if (EP == EP_BIAS || EP == EP_BIAS_GELU) v += g.bias[n];
+    if (EP == EP_GELU_GRAD) v *= gelu_grad(g.Z[o]);
+    g.C[o] = v;
+    if (EP == EP_BIAS_GELU) g.C2[o] = gelu(v);
+  }
+}
+
+template <int EP>
+hipError_t gemm(const Gemm& g, hipStream_t s) {
+  const int ncol = EP == EP_WGRAD ? g.N + 1 : g.N;
+  dim3 grid((g.M + 15) / 16, (ncol + 15) / 16);
+  gemm_kernel<EP><<<grid, 256, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+Gemm make(int M, int N, int K, const float* A, int64_t sam, int64_t sak, const float* B,
+          int64_t sbk, int64_t sbn, float* C, int64_t ldc) {
+  Gemm g;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.A = A;
+  g.sam = sam;
+  g.sak = sak;
+  g.B = B;
+  g.sbk = sbk;
+  g.sbn = sbn;
+  g.C = C;
+  g.ldc = ldc;
+  g.bias = nullptr;
+  g.C2 = nullptr;
+  g.Z = nullptr;
+  return g;
+}
+
+// ---- loss, reductions, optimizer, data movement ---------------------------
+
+// one wavefront per row: relative squared error and dL/dy_hat
+__global__ __launch_bounds__(256) void loss_kernel(const float* yh, const float* y, int64_t B,
+                                                   float eps, float* d3, float* lrow) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (row >= B) return;
+  const float* a = yh + row * kMlpOut;
+  const float* t = y + row * kMlpOut;
+  float num = 0.0f, den = 0.0f;
+  for (int j = lane; j < kMlpOut; j += 64) {
+    const float r = a[j] - t[j];
+    num += r * r;
+    den += t[j] * t[j];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    num += __shfl_xor(num, o);
+    den += __shfl_xor(den, o);
+  }
+  den += eps;
+  if (lane == 0) lrow[row] = num / den;
+  const float sc = 2.0f / (den * float(B));
+  for (int j = lane; j < kMlpOut; j += 64) d3[row * kMlpOut + j] = sc * (a[j] - t[j]);
+}
+
+// out[0] = scale * sum(x[0..n)), one block, fixed order
+__global__ __launch_bounds__(256) void sum_kernel(const float* x, int64_t n, float scale,
+                                                  float* out) {
+  __shared__ float part[256];
+  float acc = 0.0f;
+  for (int64_t i = threadIdx.x; i < n; i += 256) acc += x[i];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (int(threadIdx.x) < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = part[0] * scale;
+}
+
+__global__ void adam_kernel(float* P, const float* g, float* m, float* v, int n, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  P[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+__global__ void gather_rows_kernel(const float* X, const float* Y, const int64_t* idx, int64_t B,
+                                   int64_t n_rows, float* xo, float* yo) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t row = t / 128;
+  const int c = int(t % 128);
+  if (row >= B) return;
+  const int64_t src = min(max(idx[row], int64_t(0)), n_rows - 1);  // rows outside the set are clamped
+  if (c < kMlpIn) xo[row * kMlpIn + c] = X[src * kMlpIn + c];
+  if (c < kMlpOut) yo[row * kMlpOut + c] = Y[src * kMlpOut + c];
+}
+
+__global__ void pack_bf16_kernel(const float* P, __bf16* Wb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kBfTotal) return;
+  float v = 0.0f;
+  if (i < kBfW2) {
+    const int r = i / kS1, c = i % kS1;
+    if (c < kMlpIn) v = P[kOW1 + r * kMlpIn + c];
+  } else if (i < kBfW3) {
+    const int r = (i - kBfW2) / kS2, c = (i - kBfW2) % kS2;
+    if (c < kMlpH) v = P[kOW2 + r * kMlpH + c];
+  } else {
+    const int r = (i - kBfW3) / kS2, c = (i - kBfW3) % kS2;
+    if (r < kMlpOut && c < kMlpH) v = P[kOW3 + r * kMlpH + c];
+  }
+  Wb[i] = to_bf16(v);
+}
+
+// ---- BF16 inference core ----------------------------------------------------
+
+// Per wavefront LDS: sX [16][kS1] inputs, sH1/sH2 [16][kS2] hidden
+// activations (bf16); outputs as FP32 [16][80] over sX..sH1 once layer 2 is
+// done.
+constexpr int kWaveBytes = 16 * kS1 * 2 + 2 * 16 * kS2 * 2;
+constexpr int kWeightBytes = kBfTotal * 2;
+constexpr int kInferLds = kWeightBytes + 4 * kWaveBytes;
+static_assert(16 * 80 * 4 <= 16 * kS1 * 2 + 16 * kS2 * 2, "output tile must fit over sX, sH1");
+
+__device__ __forceinline__ void load_weights(const uint16_t* Wb, uint16_t* sW) {
+  const uint4* src = reinterpret_cast<const uint4*>(Wb);
+  uint4* dst = reinterpret_cast<uint4*>(sW);
+  for (int i = threadIdx.x; i < kWeightBytes / 16; i += blockDim.x) dst[i] = src[i];
+}
+
+// one layer: out[face][j] for 16 faces, j over mt tiles; A = W rows (LDS),
+// B = activations [face][k] (LDS)
+template <int MT, int KB, int SW, int SA>
+__device__ __forceinline__ void layer_bf16(const __bf16* W, const __bf16* act, floatx4 (&acc)[MT],
+                                           int e, int q4) {
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) acc[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    const bf16x8 b = *reinterpret_cast<const bf16x8*>(act + e * SA + kb * 32 + 8 * q4);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(W + (mt * 16 + e) * SW + kb * 32 + 8 * q4);
+      acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[mt], 0, 0, 0);
+    }
+  }
+}
+
+// Runs the network on the wavefront's 16 rows in sX; leaves the FP32 outputs
+// in sY [16][80] (normalized units).
+__device__ __forceinline__ void mlp_wave(const __bf16* sW, const float* P, __bf16* sX,
+                                         __bf16* sH1, __bf16* sH2, float* sY) {
+  const int lane = threadIdx.x & 63, e = lane & 15, q4 = lane >> 4;
+  {
+    floatx4 acc[8];
+    layer_bf16<8, 3, kS1, kS1>(sW + kBfW1, sX, acc, e, q4);
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = mt * 16 + 4 * q4 + r;
+        sH1[e * kS2 + j] = to_bf16(gelu(acc[mt][r] + P[kOB1 + j]));
+      }
+  }
+  __syncthreads();
+  {
+    floatx4 acc[8];
+    layer_bf16<8, 4, kS2, kS2>(sW + kBfW2, sH1, acc, e, q4);
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = mt * 16 + 4 * q4 + r;
+        sH2[e * kS2 + j] = to_bf16(gelu(acc[mt][r] + P[kOB2 + j]));
+      }
+  }
+  __syncthreads();
+  {
+    floatx4 acc[5];
+    layer_bf16<5, 4, kS2, kS2>(sW + kBfW3, sH2, acc, e, q4);
+#pragma unroll
+    for (int mt = 0; mt < 5; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = mt * 16 + 4 * q4 + r;
+        sY[e * 80 + j] = j < kMlpOut ? acc[mt][r] + P[kOB3 + j] : 0.0f;
+      }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void infer_kernel(const uint16_t* Wb, const float* P,
+                                                    const float* X, int64_t B, float* Y) {
+  extern __shared__ uint4 smem4[];
+  uint16_t* smem = reinterpret_cast<uint16_t*>(smem4);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __bf16* sW = reinterpret_cast<__bf16*>(smem);
+  char* wb = reinterpret_cast<char*>(smem) + kWeightBytes + w * kWaveBytes;
+  __bf16* sX = reinterpret_cast<__bf16*>(wb);
+  __bf16* sH1 = sX + 16 * kS1;
+  __bf16* sH2 = sH1 + 16 * kS2;
+  float* sY = reinterpret_cast<float*>(wb);
+  load_weights(Wb, smem);
+  const int64_t r0 = (int64_t(blockIdx.x) * 4 + w) * 16;
+  for (int i = lane; i < 16 * kS1; i += 64) {
+    const int row = i / kS1, c = i % kS1;
+    const float v = (c < kMlpIn && r0 + row < B) ? X[(r0 + row) * kMlpIn + c] : 0.0f;
+    sX[i] = to_bf16(v);
+  }
+  __syncthreads();
+  mlp_wave(sW, P, sX, sH1, sH2, sY);
+  for (int i = lane; i < 16 * kMlpOut; i += 64) {
+    const int row = i / kMlpOut, j = i % kMlpOut;
+    if (r0 + row < B) Y[(r0 + row) * kMlpOut + j] = sY[row * 80 + j];
+  }
+}
+
+// ---- learned ghost traces (N = 4) -------------------------------------------
+
+constexpr int kNp4 = 35, kNfp4 = 15;
+
+__global__ __launch_bounds__(256) void learned_ghost_kernel(DeviceMesh m, LearnedBC L,
+                                                            const float* q) {
+  extern __shared__ uint4 smem4[];
+  uint16_t* smem = reinterpret_cast<uint16_t*>(smem4);
+  __shared__ float sPmax[4][16];
+  __shared__ unsigned sBad[4][16];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __bf16* sW = reinterpret_cast<__bf16*>(smem);
+  char* wb = reinterpret_cast<char*>(smem) + kWeightBytes + w * kWaveBytes;
+  __bf16* sX = reinterpret_cast<__bf16*>(wb);
+  __bf16* sH1 = sX + 16 * kS1;
+  __bf16* sH2 = sH1 + 16 * kS2;
+  float* sY = reinterpret_cast<float*>(wb);
+  const Phys& P = m.phys;
+  load_weights(L.Wb, smem);
+  if (lane < 16) {
+    sPmax[w][lane] = 0.0f;
+    sBad[w][lane] = 0u;
+  }
+  const int64_t j0 = (int64_t(blockIdx.x) * 4 + w) * 16;
+  const float inv = 1.0f / L.norm;
+  __syncthreads();
+  // inputs: interior trace / norm (variable-major), then the normal
+  for (int i = lane; i < 16 * kS1; i += 64) {
+    const int row = i / kS1, c = i % kS1;
+    const int64_t j = j0 + row;
+    float v = 0.0f;
+    if (j < L.nl && c < kMlpIn) {
+      const int kf = L.lface[j];
+      const int64_t k = kf >> 2;
+      const int f = kf & 3;
+      if (c < 5 * kNfp4) {
+        const int var = c / kNfp4, node = m.fmask[f * kNfp4 + c % kNfp4];
+        v = q[(k * 5 + var) * kNp4 + node] * inv;
+      } else {
+        v = float(m.sgeo[k * 16 + f * 4 + (c - 5 * kNfp4)]);
+      }
+    }
+    sX[i] = to_bf16(v);
+  }
+  // max |p'| of each face's interior trace
+  for (int i = lane; i < 16 * kNfp4; i += 64) {
+    const int row = i / kNfp4, ii = i % kNfp4;
+    const int64_t j = j0 + row;
+    if (j >= L.nl) continue;
+    const int kf = L.lface[j];
+    const int64_t k = kf >> 2;
+    const int node = m.fmask[(kf & 3) * kNfp4 + ii];
+    float qm[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) qm[v] = q[(k * 5 + v) * kNp4 + node];
+    Prim wm;
+    primitive<true>(P, qm, wm);
+    atomicMax(reinterpret_cast<unsigned*>(&sPmax[w][row]), __float_as_uint(fabsf(wm.pp)));
+  }
+  __syncthreads();
+  mlp_wave(sW, L.P, sX, sH1, sH2, sY);
+  // physical check of the network state at every node
+  for (int i = lane; i < 16 * kNfp4; i += 64) {
+    const int row = i / kNfp4, ii = i % kNfp4;
+    if (j0 + row >= L.nl) continue;
+    float qg[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) qg[v] = sY[row * 80 + v * kNfp4 + ii] * L.norm;
+    Prim wg;
+    primitive<true>(P, qg, wg);
+    if (!(wg.rho > 0.0f) || !(wg.p > 0.0f)) atomicOr(&sBad[w][row], 1u);
+  }
+  __syncthreads();
+  for (int i = lane; i < 16 * kNfp4; i += 64) {
+    const int row = i / kNfp4, ii = i % kNfp4;
+    const int64_t j = j0 + row;
+    if (j >= L.nl) continue;
+    const float pm = sPmax[w][row];
+    const bool use = !sBad[w][row] && pm >= L.plo && pm <= L.phi;
+    float qg[5];
+    if (use) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) qg[v] = sY[row * 80 + v * kNfp4 + ii] * L.norm;
+    } else {
+      const int kf = L.lface[j];
+      const int64_t k = kf >> 2;
+      const int f = kf & 3;
+      const int node = m.fmask[f * kNfp4 + ii];
+      const float n[3] = {float(m.sgeo[k * 16 + f * 4 + 0]), float(m.sgeo[k * 16 + f * 4 + 1]),
+                          float(m.sgeo[k * 16 + f * 4 + 2])};
+      float qm[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) qm[v] = q[(k * 5 + v) * kNp4 + node];
+      Prim wm;
+      primitive<true>(P, qm, wm);
+      ghost(P, BC_OUTFLOW_CHAR, qm, wm, n, 0.0f, qg);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) L.ghost[(j * 5 + v) * kNp4 + ii] = qg[v];
+  }
+}
+
+// ---- trace sampler ------------------------------------------------------------
+
+template <int N>
+__global__ void sample_kernel(DeviceMesh m, const float* q, const int64_t* faces, int64_t nf,
+                              float norm, float* X, float* Y) {
+  constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t j = t / Nfp;
+  const int ii = int(t % Nfp);
+  if (j >= nf) return;
+  const int64_t kf = faces[j];
+  const int64_t k = kf >> 2;
+  const int f = int(kf & 3);
+  if (kf < 0 || k >= m.K) return;  // not a face of this mesh
+  const int node = m.fmask[f * Nfp + ii];
+  const float inv = 1.0f / norm;
+  const float n[3] = {float(m.sgeo[k * 16 + f * 4 + 0]), float(m.sgeo[k * 16 + f * 4 + 1]),
+                      float(m.sgeo[k * 16 + f * 4 + 2])};
+  float qm[5], qp[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) qm[v] = q[(k * 5 + v) * Np + node];
+  const int nb = m.nbr[k * 4 + f];
+  if (nb >= 0) {
+    const int inf = m.finfo[k * 4 + f];
+    const int n2 = m.nbr_node[((f * 4 + (inf & 3)) * 6 + (inf >> 2)) * Nfp + ii];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) qp[v] = q[(int64_t(nb) * 5 + v) * Np + n2];
+  } else {
+    Prim wm;
+    primitive<true>(m.phys, qm, wm);
+    ghost(m.phys, (-nb) & 7, qm, wm, n, 0.0f, qp);
+  }
+  const int in = 5 * Nfp + 3, out = 5 * Nfp;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    X[j * in + v * Nfp + ii] = qm[v] * inv;
+    if (Y) Y[j * out + v * Nfp + ii] = qp[v] * inv;
+  }
+  if (ii < 3) X[j * in + 5 * Nfp + ii] = n[ii];
+}
+
+}  // namespace
+
+// ---- host entry points ----------------------------------------------------------
+
+hipError_t mlp_forward_f32(const float* P, const float* X, int64_t B, const MlpWork& w, float* Y,
+                           hipStream_t s) {
+  const int b = int(B);
+  Gemm g1 = make(b, kMlpH, kMlpIn, X, kMlpIn, 1, P + kOW1, 1, kMlpIn, w.z1, kMlpH);
+  g1.bias = P + kOB1;
+  g1.C2 = w.a1;
+  hipError_t e = gemm<EP_BIAS_GELU>(g1, s);
+  Gemm g2 = make(b, kMlpH, kMlpH, w.a1, kMlpH, 1, P + kOW2, 1, kMlpH, w.z2, kMlpH);
+  g2.bias = P + kOB2;
+  g2.C2 = w.a2;
+  if (e == hipSuccess) e = gemm<EP_BIAS_GELU>(g2, s);
+  Gemm g3 = make(b, kMlpOut, kMlpH, w.a2, kMlpH, 1, P + kOW3, 1, kMlpH, Y, kMlpOut);
+  g3.bias = P + kOB3;
+  if (e == hipSuccess) e = gemm<EP_BIAS>(g3, s);
+  return e;
+}
+
+hipError_t mlp_grad_f32(const float* P, const float* X, const float* Y, int64_t B, float eps,
+                        const MlpWork& w, float* grads, float* loss_dev, hipStream_t s) {
+  const int b = int(B);
+  hipError_t e = mlp_forward_f32(P, X, B, w, w.yh, s);
+  if (e != hipSuccess) return e;
+  loss_kernel<<<int((B + 3) / 4), 256, 0, s>>>(w.yh, Y, B, eps, w.d3, w.lrow);
+  sum_kernel<<<1, 256, 0, s>>>(w.lrow, B, 1.0f / float(B), loss_dev);
+  // layer 3: dW3 = d3^T a2, db3 = sum d3; d2 = (d3 W3) * gelu'(z2)
+  Gemm w3 = make(kMlpOut, kMlpH, b, w.d3, 1, kMlpOut, w.a2, kMlpH, 1, grads + kOW3, kMlpH);
+  w3.C2 = grads + kOB3;
+  e = gemm<EP_WGRAD>(w3, s);
+  Gemm d2 = make(b, kMlpH, kMlpOut, w.d3, kMlpOut, 1, P + kOW3, kMlpH, 1, w.d2, kMlpH);
+  d2.Z = w.z2;
+  if (e == hipSuccess) e = gemm<EP_GELU_GRAD>(d2, s);
+  // layer 2
+  Gemm w2 = make(kMlpH, kMlpH, b, w.d2, 1, kMlpH, w.a1, kMlpH, 1, grads + kOW2, kMlpH);
+  w2.C2 = grads + kOB2;
+  if (e == hipSuccess) e = gemm<EP_WGRAD>(w2, s);
+  Gemm d1 = make(b, kMlpH, kMlpH, w.d2, kMlpH, 1, P + kOW2, kMlpH, 1, w.d1, kMlpH);
+  d1.Z = w.z1;
+  if (e == hipSuccess) e = gemm<EP_GELU_GRAD>(d1, s);
+  // layer 1
+  Gemm w1 = make(kMlpH, kMlpIn, b, w.d1, 1, kMlpH, X, kMlpIn, 1, grads + kOW1, kMlpIn);
+  w1.C2 = grads + kOB1;
+  if (e == hipSuccess) e = gemm<EP_WGRAD>(w1, s);
+  if (e == hipSuccess) e = hipGetLastError();
+  return e;
+}
+
+hipError_t mlp_gather_rows(const float* X, const float* Y, const int64_t* idx, int64_t B,
+                           int64_t n_rows, const MlpWork& w, hipStream_t s) {
+  const int64_t n = B * 128;
+  gather_rows_kernel<<<int((n + 255) / 256), 256, 0, s>>>(X, Y, idx, B, n_rows, w.x, w.y);
+  return hipGetLastError();
+}
+
+hipError_t mlp_adam(float* P, const float* g, float* m, float* v, float lr, float b1, float b2,
+                    float eps, float c1, float c2, hipStream_t s) {
+  adam_kernel<<<(kMlpParams + 255) / 256, 256, 0, s>>>(P, g, m, v, kMlpParams, lr, b1, b2, eps,
+                                                        c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t mlp_pack_bf16(const float* P, uint16_t* Wb, hipStream_t s) {
+  pack_bf16_kernel<<<(kBfTotal + 255) / 256, 256, 0, s>>>(P, reinterpret_cast<__bf16*>(Wb));
+  return hipGetLastError();
+}
+
+static hipError_t lds_attr(const void* fn) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kInferLds);
+}
+
+hipError_t mlp_infer_bf16(const uint16_t* Wb, const float* P, const float* X, int64_t B, float* Y,
+                          hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipError_t e = lds_attr(reinterpret_cast<const void*>(&infer_kernel));
+  if (e != hipSuccess) return e;
+  infer_kernel<<<int((B + 63) / 64), 256, kInferLds, s>>>(Wb, P, X, B, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_ghost(const DeviceMesh& m, const LearnedBC& L, const float* q,
+                                hipStream_t s) {
+  if (L.nl <= 0) return hipSuccess;
+  if (m.N != 4) return hipErrorInvalidValue;
+  hipError_t e = lds_attr(reinterpret_cast<const void*>(&learned_ghost_kernel));
+  if (e != hipSuccess) return e;
+  learned_ghost_kernel<<<int((L.nl + 63) / 64), 256, kInferLds, s>>>(m, L, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_traces(const DeviceMesh& m, const float* q, const int64_t* faces,
+                                int64_t nf, float norm, float* X, float* Y, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  const int Nfp = (m.N + 1) * (m.N + 2) / 2;
+  const int64_t n = nf * Nfp;
+  const int blocks = int((n + 255) / 256);
+  switch (m.N) {
+    case 1: sample_kernel<1><<<blocks, 256, 0, s>>>(m, q, faces, nf, norm, X, Y); break;
+    case 2: sample_kernel<2><<<blocks, 256, 0, s>>>(m, q, faces, nf, norm, X, Y); break;
+    case 3: sample_kernel<3><<<blocks, 256, 0, s>>>(m, q, faces, nf, norm, X, Y); break;
+    case 4: sample_kernel<4><<<blocks, 256, 0, s>>>(m, q, faces, nf, norm, X, Y); break;
+    case 5: sample_kernel<5><<<blocks, 256, 0, s>>>(m, q, faces, nf, norm, X, Y); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dg
