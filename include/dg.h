@@ -280,12 +280,16 @@ int dg_batch_autotune(dg_batch* b, float* const* q, float* const* res, const cha
 
 /* ---- learned boundary closure ------------------------------------------------
  * A multilayer perceptron 78 -> 128 -> 128 -> 75 with GELU activations maps a
- * boundary face's interior trace -- the perturbation q - q0 of the five
+ * boundary face's characteristic ghost (its interior trace with the incoming
+ * acoustic characteristic removed) -- the perturbation q - q0 of the five
  * conserved variables at its 15 face nodes (N = 4), variable-major
- * x[v * 15 + i], divided by a normalization amplitude -- followed by the
- * face's outward unit normal, to the exterior trace in the same units.  It
+ * x[v * 15 + i], divided by a scale -- followed by the face's outward unit
+ * normal, to the exterior trace in the same scale.  It
  * stands in for the ghost state of the boundary conditions of Section 2
  * (faces tagged DG_BC_LEARNED), with the characteristic ghost as fallback.
+ * The scale is a fixed amplitude norm > 0, or, with norm = 0, each face's
+ * own largest |q - q0| over its input trace (inputs and outputs scale
+ * together, so the learned map is amplitude-equivariant).
  * Parameters: one FP32 vector of DG_MLP_PARAMS values, W1 [128][78], b1,
  * W2 [128][128], b2, W3 [75][128], b3 (row-major, out x in).
  * Training: FP32, loss = mean over rows of |y_hat - y|^2 / (|y|^2 + 1e-6),
@@ -323,20 +327,25 @@ int dg_mlp_train_step(dg_mlp* m, const float* X, const float* Y, int64_t n_rows,
                       const int64_t* rows, int64_t B, float lr, float* loss, void* stream);
 
 /* Attach (m != NULL) or detach (m == NULL) a network to the context's faces
- * tagged DG_BC_LEARNED (N = 4 only).  norm: the trace normalization; the
- * network's ghost is used on a face when the largest |p'| of its interior
- * trace lies in [p_lo, p_hi] and the ghost has rho > 0 and p > 0 at every
- * node, else the characteristic ghost.  The network is borrowed and must
- * outlive the attachment; weight updates take effect at the next launch. */
-int dg_set_learned_bc(dg_ctx* ctx, dg_mlp* m, double norm, double p_lo, double p_hi);
+ * tagged DG_BC_LEARNED (N = 4 only).  norm: the trace normalization (0: per
+ * face, see above).  On a face whose interior trace has its largest |p'| in
+ * [p_lo, p_hi] and whose network state has rho > 0 and p > 0 at every node,
+ * the ghost is  char + blend * (network - char)  (blend in [0, 1]; 1 = the
+ * network alone), elsewhere the characteristic ghost.  The network is
+ * borrowed and must outlive the attachment; weight updates take effect at the
+ * next launch. */
+int dg_set_learned_bc(dg_ctx* ctx, dg_mlp* m, double norm, double p_lo, double p_hi,
+                      double blend);
 
 /* Number of faces tagged DG_BC_LEARNED; when faces is not NULL, writes their
  * k * 4 + f (host int64) in the order the solver indexes them. */
 int64_t dg_learned_faces(const dg_ctx* ctx, int64_t* faces);
 
 /* Network rows from a state: for faces[j] = k * 4 + f (device int64 [nf]),
- * X[j] (device FP32 [nf][78]) = interior trace / norm and normal, and when Y
- * is not NULL, Y[j] (device [nf][75]) = exterior trace / norm: the
+ * X[j] (device FP32 [nf][78]) = characteristic ghost of the interior trace /
+ * scale and the normal, and when Y is not NULL, Y[j] (device [nf][75]) =
+ * exterior trace / scale (scale = norm, or with norm = 0 the largest
+ * |q - q0| of the face's characteristic ghost): the
  * neighbour's trace on interior faces (a larger domain's solution), the ghost
  * of the face's tag on boundary faces.  Face indices outside the mesh are
  * skipped.  Asynchronous. */

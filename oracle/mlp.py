@@ -1,10 +1,11 @@
 """Learned boundary closure: the multilayer perceptron, FP64 -- TEST
 INFRASTRUCTURE ONLY (see the package docstring).
 
-A boundary face's interior trace (the perturbation q - q0 at its Nfp nodes,
-all five conserved variables, divided by a normalization amplitude) and its
-outward unit normal are mapped to the exterior (ghost) trace in the same
-normalization by
+The input of a boundary face is its interior trace with the incoming
+acoustic characteristic removed -- the characteristic ghost state of the
+interior trace, as a perturbation q - q0 at the face's Nfp nodes for all five
+conserved variables, divided by a scale -- and its outward unit normal; the
+output is the exterior (ghost) trace in the same scale:
 
     z1 = W1 x + b1,  a1 = gelu(z1),
     z2 = W2 a1 + b2, a2 = gelu(z2),
@@ -114,8 +115,57 @@ class Adam:
         return params - lr * m_hat / (np.sqrt(v_hat) + self.eps)
 
 
-def face_inputs(q_minus, normals, scale):
-    """Network input rows from interior traces q_minus [F, 5, Nfp] (perturbations)
-    and outward unit normals [F, 3]."""
+def face_scale(q_minus, norm):
+    """Normalization of each face: the fixed amplitude norm > 0, or (norm = 0)
+    the face's largest |q - q0| over the given trace [F, 5, Nfp].  [F]"""
     F = q_minus.shape[0]
-    return np.concatenate([q_minus.reshape(F, -1) / scale, normals], axis=1)
+    if norm > 0:
+        return np.full(F, float(norm))
+    return np.abs(q_minus.reshape(F, -1)).max(axis=1)
+
+
+def face_inputs(q_minus, normals, scale):
+    """Network input rows from interior traces q_minus [F, 5, Nfp] (perturbations),
+    outward unit normals [F, 3] and per-face scales [F]."""
+    F = q_minus.shape[0]
+    s = np.broadcast_to(np.asarray(scale, dtype=np.float64), (F,))
+    inv = np.where(s > 0, 1.0 / np.where(s > 0, s, 1.0), 0.0)
+    return np.concatenate([q_minus.reshape(F, -1) * inv[:, None], normals], axis=1)
+
+
+def closure(params, phys, norm, amp_range, sizes=SIZES, blend=1.0):
+    """Ghost-state callable for `euler.rhs(..., learned=...)`.
+
+    The network's input is the characteristic ghost of the interior trace
+    (the interior trace without its incoming acoustic characteristic), so a
+    network cannot hand the interior's incoming characteristic straight back
+    as the ghost's; norm: > 0 a fixed scale, 0 each face's own (face_scale of
+    that input).  Face by face: the network's exterior trace, unless the largest interior
+    pressure perturbation |p'| on the face lies outside
+    [amp_range[0] / 2, 2 amp_range[1]] (outside the trained window, which
+    includes a face the wave has not reached) or the network's state has
+    rho <= 0 or p <= 0 at a node; such faces take the characteristic ghost.
+    On the others the ghost is char + blend * (network - char).
+    qm: conserved interior traces [F, Nfp, 5] in the face-node order of the
+    network's features; n: unit normals [F, Nfp, 3].
+    """
+    from .euler import OUTFLOW_CHAR, ghost_state, primitive
+    lo, hi = 0.5 * amp_range[0], 2.0 * amp_range[1]
+    g = phys.gamma
+
+    def learned(qm, n):
+        F, Nfp = qm.shape[0], qm.shape[1]
+        qc = ghost_state(OUTFLOW_CHAR, qm, n, phys, 0.0)
+        dc = np.transpose(qc - phys.q0, (0, 2, 1))               # [F, 5, Nfp]
+        s = face_scale(dc, norm)
+        X = face_inputs(dc, n[:, 0, :], s)
+        Y, _ = forward(params, X, sizes)
+        qn = phys.q0 + np.transpose(Y.reshape(F, 5, Nfp), (0, 2, 1)) * s[:, None, None]
+        qp = qc + blend * (qn - qc)
+        pmax = np.max(np.abs(primitive(qm, g)[..., 4] - phys.p0), axis=1)
+        wp = primitive(qp, g)
+        ok = (pmax >= lo) & (pmax <= hi) & (s > 0)
+        ok &= np.all((wp[..., 0] > 0) & (wp[..., 4] > 0), axis=1)
+        return np.where(ok[:, None, None], qp, qc)
+
+    return learned

@@ -81,7 +81,7 @@ _SIGS = {
     "dg_mlp_grad": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(ctypes.c_float), _vp, _vp]),
     "dg_mlp_train_step": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, ctypes.c_float,
                                          ctypes.POINTER(ctypes.c_float), _vp]),
-    "dg_set_learned_bc": (ctypes.c_int, [_vp, _vp, _f64, _f64, _f64]),
+    "dg_set_learned_bc": (ctypes.c_int, [_vp, _vp, _f64, _f64, _f64, _f64]),
     "dg_learned_faces": (_i64, [_vp, _vp]),
     "dg_sample_traces": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, _vp, _vp, _vp]),
 }
@@ -516,9 +516,9 @@ def dg_mlp_train_step(m, X, Y, lr, rows=None, batch=None, want_loss=True, stream
     return loss.value if want_loss else None
 
 
-def dg_set_learned_bc(ctx, m, norm, p_lo, p_hi):
+def dg_set_learned_bc(ctx, m, norm, p_lo, p_hi, blend=1.0):
     _check(_lib.dg_set_learned_bc(ctx.handle, m.handle if m is not None else None, float(norm),
-                                  float(p_lo), float(p_hi)), ctx.handle)
+                                  float(p_lo), float(p_hi), float(blend)), ctx.handle)
     ctx.mlp = m          # keep the network alive while attached
 
 

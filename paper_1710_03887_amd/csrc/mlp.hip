@@ -211,6 +211,7 @@ constexpr int kWaveBytes = 16 * kS1 * 2 + 2 * 16 * kS2 * 2;
 constexpr int kWeightBytes = kBfTotal * 2;
 constexpr int kInferLds = kWeightBytes + 4 * kWaveBytes;
 static_assert(16 * 80 * 4 <= 16 * kS1 * 2 + 16 * kS2 * 2, "output tile must fit over sX, sH1");
+static_assert(16 * kMlpOut * 4 <= 2 * 16 * kS2 * 2, "input staging must fit over sH1, sH2");
 
 __device__ __forceinline__ void load_weights(const uint16_t* Wb, uint16_t* sW) {
   const uint4* src = reinterpret_cast<const uint4*>(Wb);
@@ -314,6 +315,7 @@ __global__ __launch_bounds__(256) void learned_ghost_kernel(DeviceMesh m, Learne
   extern __shared__ uint4 smem4[];
   uint16_t* smem = reinterpret_cast<uint16_t*>(smem4);
   __shared__ float sPmax[4][16];
+  __shared__ float sScale[4][16];
   __shared__ unsigned sBad[4][16];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __bf16* sW = reinterpret_cast<__bf16*>(smem);
@@ -326,56 +328,88 @@ __global__ __launch_bounds__(256) void learned_ghost_kernel(DeviceMesh m, Learne
   load_weights(L.Wb, smem);
   if (lane < 16) {
     sPmax[w][lane] = 0.0f;
+    sScale[w][lane] = 0.0f;
     sBad[w][lane] = 0u;
   }
   const int64_t j0 = (int64_t(blockIdx.x) * 4 + w) * 16;
-  const float inv = 1.0f / L.norm;
   __syncthreads();
-  // inputs: interior trace / norm (variable-major), then the normal
-  for (int i = lane; i < 16 * kS1; i += 64) {
-    const int row = i / kS1, c = i % kS1;
-    const int64_t j = j0 + row;
-    float v = 0.0f;
-    if (j < L.nl && c < kMlpIn) {
-      const int kf = L.lface[j];
-      const int64_t k = kf >> 2;
-      const int f = kf & 3;
-      if (c < 5 * kNfp4) {
-        const int var = c / kNfp4, node = m.fmask[f * kNfp4 + c % kNfp4];
-        v = q[(k * 5 + var) * kNp4 + node] * inv;
-      } else {
-        v = float(m.sgeo[k * 16 + f * 4 + (c - 5 * kNfp4)]);
-      }
-    }
-    sX[i] = to_bf16(v);
-  }
-  // max |p'| of each face's interior trace
+  // per node: max |p'| of each face's interior trace, and the characteristic
+  // ghost (the network's input: the interior trace with its incoming
+  // acoustic characteristic removed), staged as FP32 over sH1/sH2; for
+  // per-face scaling, the ghost's largest |q'| over variables and nodes
+  float* sStage = reinterpret_cast<float*>(sH1);
   for (int i = lane; i < 16 * kNfp4; i += 64) {
     const int row = i / kNfp4, ii = i % kNfp4;
     const int64_t j = j0 + row;
     if (j >= L.nl) continue;
     const int kf = L.lface[j];
     const int64_t k = kf >> 2;
-    const int node = m.fmask[(kf & 3) * kNfp4 + ii];
-    float qm[5];
+    const int f = kf & 3;
+    const int node = m.fmask[f * kNfp4 + ii];
+    const float n[3] = {float(m.sgeo[k * 16 + f * 4 + 0]), float(m.sgeo[k * 16 + f * 4 + 1]),
+                        float(m.sgeo[k * 16 + f * 4 + 2])};
+    float qm[5], qc[5], big = 0.0f;
 #pragma unroll
     for (int v = 0; v < 5; ++v) qm[v] = q[(k * 5 + v) * kNp4 + node];
     Prim wm;
     primitive<true>(P, qm, wm);
+    ghost(P, BC_OUTFLOW_CHAR, qm, wm, n, 0.0f, qc);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      sStage[row * kMlpOut + v * kNfp4 + ii] = qc[v];
+      big = fmaxf(big, fabsf(qc[v]));
+    }
     atomicMax(reinterpret_cast<unsigned*>(&sPmax[w][row]), __float_as_uint(fabsf(wm.pp)));
+    atomicMax(reinterpret_cast<unsigned*>(&sScale[w][row]), __float_as_uint(big));
+  }
+  __syncthreads();
+  if (lane < 16 && L.norm > 0.0f) sScale[w][lane] = L.norm;
+  __syncthreads();
+  // inputs: characteristic ghost / scale (variable-major), then the normal
+  for (int i = lane; i < 16 * kS1; i += 64) {
+    const int row = i / kS1, c = i % kS1;
+    const int64_t j = j0 + row;
+    float v = 0.0f;
+    if (j < L.nl && c < kMlpIn) {
+      if (c < 5 * kNfp4) {
+        const float sc = sScale[w][row];
+        v = sc > 0.0f ? sStage[row * kMlpOut + c] / sc : 0.0f;
+      } else {
+        const int kf = L.lface[j];
+        v = float(m.sgeo[(kf >> 2) * 16 + (kf & 3) * 4 + (c - 5 * kNfp4)]);
+      }
+    }
+    sX[i] = to_bf16(v);
   }
   __syncthreads();
   mlp_wave(sW, L.P, sX, sH1, sH2, sY);
-  // physical check of the network state at every node
+  // learned ghost = characteristic ghost + blend * (scale * network output -
+  // characteristic ghost); kept in sY, with a physical check at every node
   for (int i = lane; i < 16 * kNfp4; i += 64) {
     const int row = i / kNfp4, ii = i % kNfp4;
-    if (j0 + row >= L.nl) continue;
-    float qg[5];
+    const int64_t j = j0 + row;
+    if (j >= L.nl) continue;
+    const int kf = L.lface[j];
+    const int64_t k = kf >> 2;
+    const int f = kf & 3;
+    const int node = m.fmask[f * kNfp4 + ii];
+    const float n[3] = {float(m.sgeo[k * 16 + f * 4 + 0]), float(m.sgeo[k * 16 + f * 4 + 1]),
+                        float(m.sgeo[k * 16 + f * 4 + 2])};
+    float qm[5], qg[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) qg[v] = sY[row * 80 + v * kNfp4 + ii] * L.norm;
+    for (int v = 0; v < 5; ++v) qm[v] = q[(k * 5 + v) * kNp4 + node];
+    Prim wm;
+    primitive<true>(P, qm, wm);
+    ghost(P, BC_OUTFLOW_CHAR, qm, wm, n, 0.0f, qg);
+    const float sc = sScale[w][row];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      qg[v] += L.blend * (sc * sY[row * 80 + v * kNfp4 + ii] - qg[v]);
+      sY[row * 80 + v * kNfp4 + ii] = qg[v];
+    }
     Prim wg;
     primitive<true>(P, qg, wg);
-    if (!(wg.rho > 0.0f) || !(wg.p > 0.0f)) atomicOr(&sBad[w][row], 1u);
+    if (!(wg.rho > 0.0f) || !(wg.p > 0.0f) || !(sc > 0.0f)) atomicOr(&sBad[w][row], 1u);
   }
   __syncthreads();
   for (int i = lane; i < 16 * kNfp4; i += 64) {
@@ -387,7 +421,7 @@ __global__ __launch_bounds__(256) void learned_ghost_kernel(DeviceMesh m, Learne
     float qg[5];
     if (use) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) qg[v] = sY[row * 80 + v * kNfp4 + ii] * L.norm;
+      for (int v = 0; v < 5; ++v) qg[v] = sY[row * 80 + v * kNfp4 + ii];
     } else {
       const int kf = L.lface[j];
       const int64_t k = kf >> 2;
@@ -409,41 +443,55 @@ __global__ __launch_bounds__(256) void learned_ghost_kernel(DeviceMesh m, Learne
 
 // ---- trace sampler ------------------------------------------------------------
 
+// one wavefront per face, lane = face node
 template <int N>
-__global__ void sample_kernel(DeviceMesh m, const float* q, const int64_t* faces, int64_t nf,
-                              float norm, float* X, float* Y) {
+__global__ __launch_bounds__(256) void sample_kernel(DeviceMesh m, const float* q,
+                                                     const int64_t* faces, int64_t nf, float norm,
+                                                     float* X, float* Y) {
   constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t j = t / Nfp;
-  const int ii = int(t % Nfp);
+  static_assert(Nfp <= 64, "one wavefront per face");
+  const int ii = threadIdx.x & 63;
+  const int64_t j = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (j >= nf) return;
   const int64_t kf = faces[j];
   const int64_t k = kf >> 2;
   const int f = int(kf & 3);
   if (kf < 0 || k >= m.K) return;  // not a face of this mesh
-  const int node = m.fmask[f * Nfp + ii];
-  const float inv = 1.0f / norm;
-  const float n[3] = {float(m.sgeo[k * 16 + f * 4 + 0]), float(m.sgeo[k * 16 + f * 4 + 1]),
-                      float(m.sgeo[k * 16 + f * 4 + 2])};
-  float qm[5], qp[5];
+  const bool node_lane = ii < Nfp;
+  float qm[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, qp[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  float n[3] = {float(m.sgeo[k * 16 + f * 4 + 0]), float(m.sgeo[k * 16 + f * 4 + 1]),
+                float(m.sgeo[k * 16 + f * 4 + 2])};
+  float big = 0.0f, qc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  if (node_lane) {
+    const int node = m.fmask[f * Nfp + ii];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) qm[v] = q[(k * 5 + v) * Np + node];
-  const int nb = m.nbr[k * 4 + f];
-  if (nb >= 0) {
-    const int inf = m.finfo[k * 4 + f];
-    const int n2 = m.nbr_node[((f * 4 + (inf & 3)) * 6 + (inf >> 2)) * Nfp + ii];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) qp[v] = q[(int64_t(nb) * 5 + v) * Np + n2];
-  } else {
+    for (int v = 0; v < 5; ++v) qm[v] = q[(k * 5 + v) * Np + node];
     Prim wm;
     primitive<true>(m.phys, qm, wm);
-    ghost(m.phys, (-nb) & 7, qm, wm, n, 0.0f, qp);
-  }
-  const int in = 5 * Nfp + 3, out = 5 * Nfp;
+    ghost(m.phys, BC_OUTFLOW_CHAR, qm, wm, n, 0.0f, qc);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    X[j * in + v * Nfp + ii] = qm[v] * inv;
-    if (Y) Y[j * out + v * Nfp + ii] = qp[v] * inv;
+    for (int v = 0; v < 5; ++v) big = fmaxf(big, fabsf(qc[v]));
+    const int nb = m.nbr[k * 4 + f];
+    if (nb >= 0) {
+      const int inf = m.finfo[k * 4 + f];
+      const int n2 = m.nbr_node[((f * 4 + (inf & 3)) * 6 + (inf >> 2)) * Nfp + ii];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) qp[v] = q[(int64_t(nb) * 5 + v) * Np + n2];
+    } else {
+      ghost(m.phys, (-nb) & 7, qm, wm, n, 0.0f, qp);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) big = fmaxf(big, __shfl_xor(big, o));
+  const float sc = norm > 0.0f ? norm : big;
+  const float inv = sc > 0.0f ? 1.0f / sc : 0.0f;
+  const int in = 5 * Nfp + 3, out = 5 * Nfp;
+  if (node_lane) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      X[j * in + v * Nfp + ii] = qc[v] * inv;
+      if (Y) Y[j * out + v * Nfp + ii] = qp[v] * inv;
+    }
   }
   if (ii < 3) X[j * in + 5 * Nfp + ii] = n[ii];
 }
@@ -543,9 +591,7 @@ hipError_t launch_learned_ghost(const DeviceMesh& m, const LearnedBC& L, const f
 hipError_t launch_sample_traces(const DeviceMesh& m, const float* q, const int64_t* faces,
                                 int64_t nf, float norm, float* X, float* Y, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
-  const int Nfp = (m.N + 1) * (m.N + 2) / 2;
-  const int64_t n = nf * Nfp;
-  const int blocks = int((n + 255) / 256);
+  const int blocks = int((nf + 3) / 4);
   switch (m.N) {
     case 1: sample_kernel<1><<<blocks, 256, 0, s>>>(m, q, faces, nf, norm, X, Y); break;
     case 2: sample_kernel<2><<<blocks, 256, 0, s>>>(m, q, faces, nf, norm, X, Y); break;

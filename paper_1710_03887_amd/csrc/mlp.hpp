@@ -75,25 +75,30 @@ hipError_t mlp_infer_bf16(const uint16_t* Wb, const float* P, const float* X, in
 
 // Learned ghost traces for the faces of a context tagged learned: for face
 // j = (k, f) = lface[j], from the interior trace of q (perturbation
-// [K][5][Np]) the network's exterior trace, or the characteristic ghost when
-// the face's max |p'| is outside [plo, phi] or the network state is
-// non-physical; written to ghost[j][5][Np] at nodes 0..Nfp-1 (the neighbour
-// layout of the stage kernel's gathers).
+// [K][5][Np]) the characteristic ghost moved by `blend` toward the network's
+// exterior trace (its input: that characteristic ghost, scaled), or the characteristic ghost alone when the face's max |p'|
+// is outside [plo, phi] or the network state is non-physical; written to
+// ghost[j][5][Np] at nodes 0..Nfp-1 (the neighbour layout of the stage
+// kernel's gathers).
 struct LearnedBC {
   const uint16_t* Wb = nullptr;
   const float* P = nullptr;
   const int32_t* lface = nullptr;  // [nl] k * 4 + f
   int64_t nl = 0;
   float* ghost = nullptr;          // [nl][5][Np]
-  float norm = 1.0f;               // trace normalization (inputs and outputs)
+  float norm = 0.0f;               // input scale: > 0 fixed, else each face's max |q'| of its input
   float plo = 0.0f, phi = 0.0f;    // window of max |p'| where the network is used
+  float blend = 1.0f;              // ghost = char + blend * (network - char)
 };
 hipError_t launch_learned_ghost(const DeviceMesh& m, const LearnedBC& L, const float* q,
                                 hipStream_t s);
 
-// Network input rows X [nf][78] (and, when Y is not null, exterior traces
-// Y [nf][75]) for faces faces[j] = k * 4 + f of q.  Interior faces take the
-// neighbour trace; boundary faces the ghost of their tag at inflow pressure 0.
+// Network input rows X [nf][78] (the characteristic ghost of the interior
+// trace, then the normal) and, when Y is not null, exterior traces Y [nf][75]
+// for faces faces[j] = k * 4 + f of q, both divided by `norm` (> 0) or by the
+// largest |q'| of the face's characteristic ghost (norm <= 0).  Interior faces
+// take the neighbour trace; boundary faces the ghost of their tag at inflow
+// pressure 0.
 hipError_t launch_sample_traces(const DeviceMesh& m, const float* q, const int64_t* faces,
                                 int64_t nf, float norm, float* X, float* Y, hipStream_t s);
 

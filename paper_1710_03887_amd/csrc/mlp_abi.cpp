@@ -192,14 +192,16 @@ int dg_mlp_train_step(dg_mlp* m, const float* X, const float* Y, int64_t n_rows,
   return loss ? read_loss(m, loss, s) : DG_OK;
 }
 
-int dg_set_learned_bc(dg_ctx* c, dg_mlp* m, double norm, double p_lo, double p_hi) {
+int dg_set_learned_bc(dg_ctx* c, dg_mlp* m, double norm, double p_lo, double p_hi,
+                      double blend) {
   if (!c) return DG_EINVAL;
   if (c->host_only) {
     c->err = "context was created host-only";
     return DG_ENODEV;
   }
-  if (m && (c->dm.N != 4 || !(norm > 0.0) || !(p_lo >= 0.0) || !(p_hi >= p_lo))) {
-    c->err = "the learned closure needs N = 4, norm > 0 and 0 <= p_lo <= p_hi";
+  if (m && (c->dm.N != 4 || !(norm >= 0.0) || !(p_lo >= 0.0) || !(p_hi >= p_lo) ||
+            !(blend >= 0.0 && blend <= 1.0))) {
+    c->err = "the learned closure needs N = 4, norm >= 0, 0 <= p_lo <= p_hi, 0 <= blend <= 1";
     return DG_EINVAL;
   }
   c->mlp = m;
@@ -208,6 +210,7 @@ int dg_set_learned_bc(dg_ctx* c, dg_mlp* m, double norm, double p_lo, double p_h
   c->lbc.norm = float(norm);
   c->lbc.plo = float(p_lo);
   c->lbc.phi = float(p_hi);
+  c->lbc.blend = float(blend);
   c->dm.lghost = (m && c->lbc.nl > 0) ? c->lbc.ghost : nullptr;
   if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
   c->two_steps = dg::GraphCache{};
@@ -228,7 +231,7 @@ int dg_sample_traces(dg_ctx* c, const float* q, const int64_t* faces, int64_t nf
     c->err = "context was created host-only";
     return DG_ENODEV;
   }
-  if (!q || !faces || !X || nf < 0 || !(norm > 0.0)) {
+  if (!q || !faces || !X || nf < 0 || !(norm >= 0.0)) {
     c->err = "bad argument";
     return DG_EINVAL;
   }

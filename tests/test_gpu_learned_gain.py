@@ -1,0 +1,49 @@
+"""The learned boundary closure against the characteristic ghost on the
+trumpet scene: traces sampled from a domain three times larger, a network
+trained on them by the library's kernels, its blend toward the
+characteristic ghost picked at one amplitude outside the training set, then
+the truncated box run with either ghost in lockstep with the larger domain
+at another such amplitude.  The learned ghost must leave a smaller interior
+reflection error (the larger domain's solution is the judge).  Amplitudes
+stay at or below 3% of p0: without a limiter, stronger pulses steepen into
+shocks in the bore on these coarse meshes and the solution breaks down.
+
+Coarse meshes (about 12k / 30k tetrahedra, N = 4) keep the test near a
+minute; the same workflow at 50k tetrahedra is
+`python -m paper_1710_03887_amd.learned_bc`."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.timeout(600)
+def test_learned_closure_beats_characteristic():
+    from paper_1710_03887_amd import learned_bc as lb
+    scene = lb.Scene(8000)
+    t_end = 3.0
+    Xs, Ys, Ls, dt = [], [], [], None
+    for a in (0.002, 0.005, 0.01, 0.03):
+        X, Y, L, dt = lb.sample_run(scene, a * lb.P0, t_end, dt=dt)
+        assert X is not None
+        Xs.append(X)
+        Ys.append(Y)
+        Ls.append(L)
+        print(f"amp {a}: {X.shape[0]} samples", flush=True)
+    X, Y = torch.cat(Xs), torch.cat(Ys)
+    win = lb.window_of(torch.cat(Ls))
+    net, trace = lb.train(X, Y, steps=3000, log_every=500)
+    print("loss", trace, flush=True)
+    assert trace[-1][1] < trace[0][1] / 10
+    # the blend toward the network is picked at one held-out amplitude ...
+    blend, table, _ = lb.choose_blend(scene, net, win, 0.007 * lb.P0, t_end, dt,
+                                      blends=(0.5, 0.75, 1.0))
+    print("blend", blend, table, flush=True)
+    # ... and judged at another
+    errs, secs = lb.reflection_error(scene, 0.02 * lb.P0, t_end, dt, nets=[net], window=win,
+                                     blends=[blend])
+    print(f"interior reflection error: char {errs[0]:.4e}, learned {errs[1]:.4e} "
+          f"(gain {errs[0] / errs[1]:.2f}); s/step {secs}", flush=True)
+    assert errs[1] < errs[0]

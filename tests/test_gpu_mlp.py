@@ -142,53 +142,61 @@ def _learned_pair(seed=0):
     return pair, euler.initial_state(prim, phys.gamma)
 
 
-def test_sample_traces_match_oracle():
-    """Every face of the mesh: X = interior trace / norm and normal; Y = the
+@pytest.mark.parametrize("norm", [0.1 / 1.4, 0.0])
+def test_sample_traces_match_oracle(norm):
+    """Every face of the mesh: X = characteristic ghost of the interior
+    trace / scale and the normal; Y = exterior trace / scale: the
     neighbour's trace on interior faces, the ghost of the tag on boundary
-    faces (learned faces without a network: the characteristic ghost)."""
+    faces (learned faces without a network: the characteristic ghost, so
+    Y equals X's trace part there); scale = norm, or the largest |q'| of
+    each face's characteristic ghost when norm = 0."""
     pair, q = _learned_pair(1)
     phys = pair.phys
     K = pair.mesh.K
     faces = np.arange(4 * K, dtype=np.int64)
-    norm = 0.1 * phys.p0
     X = torch.empty((4 * K, 78), dtype=torch.float32, device="cuda")
     Y = torch.empty((4 * K, 75), dtype=torch.float32, device="cuda")
     dg.dg_sample_traces(pair.ctx, pair.to_device(q), torch.tensor(faces, device="cuda"), norm, X, Y)
     torch.cuda.synchronize()
     char = lambda qm, n: euler.ghost_state(euler.OUTFLOW_CHAR, qm, n, phys, 0.0)  # noqa: E731
-    qm, qp, _ = euler.face_traces(pair.mesh, q, 0.0, phys, learned=char)   # [K, 4, Nfp, 5]
-    dm = np.transpose(qm - phys.q0, (0, 1, 3, 2)).reshape(4 * K, -1) / norm
-    dp = np.transpose(qp - phys.q0, (0, 1, 3, 2)).reshape(4 * K, -1) / norm
-    Xo = np.concatenate([dm, pair.mesh.normals.reshape(4 * K, 3)], axis=1)
+    qm, qp, nrm = euler.face_traces(pair.mesh, q, 0.0, phys, learned=char)   # [K, 4, Nfp, 5]
+    qc = char(qm, nrm)                           # the network's input: characteristic ghost
+    dc = np.transpose(qc - phys.q0, (0, 1, 3, 2)).reshape(4 * K, -1)
+    sc = omlp.face_scale(dc, norm)
+    dc = dc / sc[:, None]
+    dp = np.transpose(qp - phys.q0, (0, 1, 3, 2)).reshape(4 * K, -1) / sc[:, None]
+    Xo = np.concatenate([dc, pair.mesh.normals.reshape(4 * K, 3)], axis=1)
     assert np.abs(X.cpu().numpy() - Xo).max() < 1e-5 * np.abs(Xo).max()
     assert np.abs(Y.cpu().numpy() - dp).max() < 1e-4 * np.abs(dp).max()
+    lrn = pair.mesh.bc.ravel() == BC_LEARNED
+    assert np.abs(dp[lrn] - dc[lrn]).max() < 1e-12
     # the learned-face list is exactly the faces tagged learned
     lf = dg.dg_learned_faces(pair.ctx)
     tagged = np.nonzero(pair.mesh.bc.ravel() == BC_LEARNED)[0]
     assert np.array_equal(np.sort(lf), tagged)
 
 
-def _closure_setup(pair, window):
+def _closure_setup(pair, window, norm=0.1 / 1.4, blend=1.0):
     p = _params(4)
     # damp the output layer so the network's ghost stays near the ambient state
     o3 = 128 * 78 + 128 + 128 * 128 + 128
     p[o3:] *= 0.05
     m = dg.dg_mlp_create(p)
-    norm = 0.1 * pair.phys.p0
-    dg.dg_set_learned_bc(pair.ctx, m, norm, *window)
+    dg.dg_set_learned_bc(pair.ctx, m, norm, *window, blend=blend)
     return p, m, norm
 
 
-def test_learned_ghost_rhs_matches_oracle():
+@pytest.mark.parametrize("norm,blend", [(0.1 / 1.4, 1.0), (0.0, 1.0), (0.0, 0.6)])
+def test_learned_ghost_rhs_matches_oracle(norm, blend):
     pair, q = _learned_pair(2)
     phys = pair.phys
     window = (1e-4, 1.0)            # every face with a pulse on it uses the network
-    p, m, norm = _closure_setup(pair, window)
+    p, m, norm = _closure_setup(pair, window, norm, blend)
     qd = pair.to_device(q)
     rd = torch.empty_like(qd)
     dg.dg_rhs(pair.ctx, qd, rd, 0.0)
     torch.cuda.synchronize()
-    closure = omlp.closure(p.astype(np.float64), phys, norm, (2e-4, 0.5))
+    closure = omlp.closure(p.astype(np.float64), phys, norm, (2e-4, 0.5), blend=blend)
     r_or = euler.rhs(pair.mesh, q, 0.0, phys, learned=closure)
     r_char = euler.rhs(pair.mesh, q, 0.0, phys,
                        learned=lambda qm, n: euler.ghost_state(euler.OUTFLOW_CHAR, qm, n, phys, 0.0))

@@ -108,3 +108,21 @@ def test_adam_closed_forms():
     v = 0.999 * 0.001 + 0.001
     step = (m / (1 - 0.81)) / (np.sqrt(v / (1 - 0.999 ** 2)) + 1e-8)
     assert abs((p2 - p1)[0] + step) < 1e-14
+
+
+def test_per_face_scaling_is_amplitude_equivariant():
+    """With per-face scaling the network sees the same rows for c * q' as
+    for q', so its ghost perturbation scales by exactly c."""
+    rng = np.random.default_rng(3)
+    dq = rng.normal(size=(6, 5, 15))
+    n = rng.normal(size=(6, 3))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    s = mlp.face_scale(dq, 0.0)
+    assert np.allclose(s, np.abs(dq.reshape(6, -1)).max(axis=1))
+    X1 = mlp.face_inputs(dq, n, s)
+    X2 = mlp.face_inputs(1e-3 * dq, n, mlp.face_scale(1e-3 * dq, 0.0))
+    assert np.allclose(X1, X2, rtol=1e-13, atol=0)
+    assert np.max(np.abs(X1[:, :75])) == 1.0
+    # a fixed norm divides every face by the same amplitude
+    assert np.allclose(mlp.face_inputs(dq, n, mlp.face_scale(dq, 0.5))[:, :75],
+                       dq.reshape(6, -1) / 0.5)
