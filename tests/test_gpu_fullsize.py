@@ -1,0 +1,48 @@
+"""Parity at the benchmark's full size: the trumpet in the box at 207,900
+tetrahedra, N = 4, in the launch configuration bench.py times (autotuned
+resident blocks per CU), every element's right-hand side against the FP64
+oracle (about half a minute of CPU work).  The state is a pressure bump in
+the bell mouth with a small cross flow at the time the inflow pulse is at
+its peak, so interior faces, slip walls, the mouthpiece inflow and the
+characteristic outflow all carry signal.  Bars as for the small cases: FP32
+2e-5, split-BF16 2e-3 relative L2 over all variables (see
+test_gpu_parity.py and test_gpu_bf16.py for their derivation)."""
+import numpy as np
+import pytest
+
+import paper_1710_03887_amd as dg
+from oracle import euler
+from workloads import trumpet_domain, gaussian_pulse
+from helpers import Pair, rel_l2, phys_kwargs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+ALPHA = 2 * np.pi * 565.0 / 343.0
+
+
+@pytest.mark.timeout(400)
+def test_rhs_parity_full_size_trumpet():
+    m = trumpet_domain("box", 200_000)
+    phys = euler.Physics(amp=0.1 / 1.4, alpha=ALPHA)
+    pair = Pair(m, 4, phys)
+    assert pair.mesh.K == 207_900
+    prim = gaussian_pulse(pair.mesh.x, 0.05 * phys.p0, 0.2, (1.1, 0.1, 0.0), phys.rho0, phys.p0,
+                          phys.gamma)
+    prim[..., 2] += 0.02 * np.exp(-((pair.mesh.x[..., 0] - 1.2) ** 2) / 0.3)
+    q = euler.initial_state(prim, phys.gamma)
+    t_peak = np.pi / ALPHA
+    r_or = euler.rhs(pair.mesh, q, t_peak, phys)
+    qd = pair.to_device(q)
+    for precision, tol in ((dg.DG_FP32, 2e-5), (dg.DG_SPLIT_BF16, 2e-3)):
+        ctx = pair.ctx if precision == dg.DG_FP32 else dg.dg_mesh_setup(
+            m["xyz"], m["EToV"], m["bc"], 4, precision=precision, **phys_kwargs(phys))
+        res = torch.zeros_like(qd)
+        dg.dg_autotune(ctx, qd, res)
+        rd = torch.empty_like(qd)
+        dg.dg_rhs(ctx, qd, rd, t_peak)
+        torch.cuda.synchronize()
+        err = rel_l2(pair.mesh, pair.rates_from_device(rd), r_or)
+        print(f"precision {precision}: rhs rel L2 {err:.3e} over {pair.mesh.K} elements", flush=True)
+        assert err < tol
