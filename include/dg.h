@@ -263,9 +263,19 @@ int dg_batch_set_launch(dg_batch* b, int blocks_per_cu, int waves_per_block);
  * fit); used by the autotuner. */
 int dg_set_launch(dg_ctx* ctx, int blocks_per_cu);
 
+/* Stage kernel of a single-solve context: 0 = tile-cooperative (four
+ * wavefronts share a 16-element tile and split the contraction), 1 =
+ * wavefront-private (each wavefront owns a 16-element tile; FP32 form,
+ * N <= 4).  Same results up to floating-point summation order.  Used by the
+ * autotuner; DG_EINVAL when the variant does not apply. */
+int dg_set_kernel(dg_ctx* ctx, int variant);
+int dg_get_kernel(const dg_ctx* ctx);
+
 /* ---- launch-shape autotuner -------------------------------------------------
- * Times every launch shape of the stage kernel (resident blocks per CU; for
- * batches also wavefronts per block) on the caller's stream with HIP events,
+ * Times every launch shape of the stage kernel (resident blocks per CU, and
+ * the stage-kernel variant where the wavefront-private one applies; for
+ * batches blocks per CU and wavefronts per block) on the caller's stream
+ * with HIP events,
  * applies the fastest and appends it to the text cache at cache_path (NULL or
  * "" for no cache) under a key made of the workload sizes and the device
  * architecture and CU count; a cached entry is applied without timing.

@@ -71,6 +71,8 @@ _SIGS = {
     "dg_batch_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                          ctypes.c_char_p, ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int), _vp]),
+    "dg_set_kernel": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "dg_get_kernel": (ctypes.c_int, [_vp]),
     "dg_run_fixed": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, ctypes.POINTER(_f64), _vp]),
     "dg_mlp_create": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),
     "dg_mlp_destroy": (ctypes.c_int, [_vp]),
@@ -277,6 +279,14 @@ def dg_state_to_prim(ctx, q, prim, stream=None):
     _check_state(ctx, q, "q")
     _check_state(ctx, prim, "prim")
     _check(_lib.dg_state_to_prim(ctx.handle, _ptr(q), _ptr(prim), _stream(stream)), ctx.handle)
+
+
+def dg_set_kernel(ctx, variant):
+    _check(_lib.dg_set_kernel(ctx.handle, int(variant)), ctx.handle)
+
+
+def dg_get_kernel(ctx):
+    return int(_lib.dg_get_kernel(ctx.handle))
 
 
 def dg_set_launch(ctx, blocks_per_cu):

@@ -440,6 +440,20 @@ int dg_run_fixed(dg_ctx* c, float* q, float* res, int64_t nsteps, double dt, dou
 
 int64_t dg_last_step(const dg_ctx* c) { return c ? c->last_bad : -1; }
 
+int dg_set_kernel(dg_ctx* c, int variant) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (variant != 0 && variant != 1) return fail(c, DG_EINVAL, "variant must be 0 or 1");
+  if (variant == 1 && !dg::wave_stage_supported(c->dm.N, c->dm.precision))
+    return fail(c, DG_EINVAL, "the wavefront-private stage kernel needs the FP32 form and N <= 4");
+  c->dm.variant = variant;
+  if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
+  c->two_steps = dg::GraphCache{};
+  return DG_OK;
+}
+
+int dg_get_kernel(const dg_ctx* c) { return c ? c->dm.variant : -1; }
+
 int dg_set_launch(dg_ctx* c, int blocks_per_cu) {
   int rc = need_device(c);
   if (rc) return rc;

@@ -1,8 +1,10 @@
 // Launch-shape autotuner for the stage kernels.  Every candidate shape is
 // timed with HIP events on the caller's stream over a few stage launches;
 // the fastest is kept and recorded in a plain-text cache (one line per
-// workload: key, blocks per CU, waves per block, microseconds), so that a
-// later process with the same workload and device skips the search.
+// workload: key, two launch parameters, microseconds -- blocks per CU and
+// stage-kernel variant for a single solution, blocks per CU and waves per
+// block for an ensemble), so that a later process with the same workload and
+// device skips the search.
 // Results never depend on the launch shape: elements are independent and
 // every reduction is a maximum.
 #include <hip/hip_runtime.h>
@@ -99,11 +101,19 @@ int dg_autotune(dg_ctx* c, const float* q, float* res, const char* cache_path, i
   hipStream_t s = static_cast<hipStream_t>(stream);
   const std::string key = "single/N" + std::to_string(c->dm.N) + "/K" + std::to_string(c->dm.K) +
                           "/prec" + std::to_string(c->dm.precision) + "/" + device_key();
-  int best = 0, unused = 0;
-  if (!cache_lookup(cache_path, key, &best, &unused) || best < 1 || best > c->max_blocks_per_cu) {
+  const bool wave_ok = dg::wave_stage_supported(c->dm.N, c->dm.precision);
+  int best = 0, best_v = 0;
+  if (!cache_lookup(cache_path, key, &best, &best_v) || best < 1 ||
+      best > c->max_blocks_per_cu || best_v < 0 || best_v > 1 || (best_v == 1 && !wave_ok)) {
     double best_us = 1e300;
-    for (int bpc = 1; bpc <= c->max_blocks_per_cu; ++bpc) {
+    // the tile-cooperative kernel at every residency, then the
+    // wavefront-private kernel (one block of eight wavefronts per CU)
+    const int ncand = c->max_blocks_per_cu + (wave_ok ? 1 : 0);
+    for (int cand = 0; cand < ncand; ++cand) {
+      const int variant = cand < c->max_blocks_per_cu ? 0 : 1;
+      const int bpc = variant == 0 ? cand + 1 : 1;
       c->dm.blocks_per_cu = bpc;
+      c->dm.variant = variant;
       hipError_t err = hipSuccess;
       const double us = time_launch(
           [&] {
@@ -119,11 +129,13 @@ int dg_autotune(dg_ctx* c, const float* q, float* res, const char* cache_path, i
       if (us < best_us) {
         best_us = us;
         best = bpc;
+        best_v = variant;
       }
     }
-    cache_store(cache_path, key, best, 4, best_us);
+    cache_store(cache_path, key, best, best_v, best_us);
   }
   c->dm.blocks_per_cu = best;
+  c->dm.variant = best_v;
   if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
   c->two_steps = dg::GraphCache{};
   if (blocks_per_cu) *blocks_per_cu = best;

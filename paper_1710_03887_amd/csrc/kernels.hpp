@@ -28,6 +28,7 @@ struct DeviceMesh {
   // learned ghost traces [n_learned][5][Np] (nodes 0..Nfp-1), or null; a
   // learned face's nbr entry is -(BC_LEARNED + 8 * its index)
   const float* lghost = nullptr;
+  int variant = 0;                  // stage kernel: 0 tile-cooperative, 1 wavefront-private
   Phys phys;
 };
 
@@ -54,6 +55,13 @@ enum StageMode : int { MODE_RHS = 0, MODE_STAGE = 1 };
 hipError_t launch_stage(const DeviceMesh& m, int mode, const float* q_in, float* q_out,
                         float* res, float* out, float a, float b, double c, double t_host,
                         double dt_host, RunScalars* run, int rate_out, hipStream_t s);
+
+// The wavefront-private stage kernel (same contract as launch_stage), for
+// the FP32 form at N <= 4.
+bool wave_stage_supported(int N, int precision);
+hipError_t launch_wave_stage(const DeviceMesh& m, int mode, const float* q_in, float* q_out,
+                             float* res, float* out, float a, float b, double c, double t_host,
+                             double dt_host, RunScalars* run, int rate_out, hipStream_t s);
 
 // Max of (N+1)^2/2 Fscale (|u|+c) over interior face traces into
 // run->rate_bits (as ordered float bits); flags non-physical traces.
