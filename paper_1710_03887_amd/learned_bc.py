@@ -40,6 +40,7 @@ class Scene:
     def __init__(self, target_K=8000, scale=3.0):
         from workloads.trumpet import trumpet_nested
         from workloads import BC_OUTFLOW_CHAR
+        self.target_K = target_K
         self.big, self.small, self.emap = trumpet_nested(target_K, scale)
         k, f = np.nonzero(self.small["bc"] == BC_OUTFLOW_CHAR)
         self.small_faces = (k, f)
@@ -170,6 +171,50 @@ def reflection_error(scene, amp, t_end, dt, nets=(), every=100, window=None, ble
     return errs, [s / nsteps for s in secs]
 
 
+def char_domains(scene, amp, t_end, dt, scales, every=100):
+    """Interior error of the characteristic ghost on outer boxes `scales`
+    times the small box (each containing the small mesh element for
+    element), judged like reflection_error against the scene's larger
+    domain on the small box's elements.  Returns ([error per scale],
+    [seconds per step per scale], [elements per scale])."""
+    torch = _torch()
+    from workloads.trumpet import trumpet_nested
+    big = scene.context("big", amp)
+    runs, maps = [], []
+    for sc in scales:
+        mid, small, emap = trumpet_nested(scene.target_K, sc)
+        assert np.array_equal(small["EToV"], scene.small["EToV"])
+        runs.append(dg.dg_mesh_setup(mid["xyz"], mid["EToV"], mid["bc"], 4, gamma=GAMMA, rho0=RHO0,
+                                     p0=P0, inflow_amp=amp, inflow_alpha=ALPHA))
+        maps.append(torch.tensor(emap, dtype=torch.int64, device="cuda"))
+    emap_big = torch.tensor(scene.emap, dtype=torch.int64, device="cuda")
+    Js = _weights(big)[emap_big]
+    states = []
+    for c in [big] + runs:
+        q = torch.zeros((c.K, 5, c.Np), dtype=torch.float32, device="cuda")
+        states.append((c, q, torch.zeros_like(q), torch.empty_like(q)))
+    num, den, secs = [0.0] * len(runs), 0.0, [0.0] * len(runs)
+    t = [0.0] * len(states)
+    nsteps, done = int(t_end / dt), 0
+    while done < nsteps:
+        n = min(every, nsteps - done)
+        for i, (c, q, r, prim) in enumerate(states):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t[i] = dg.dg_run_fixed(c, q, r, n, dt, t[i])
+            if i > 0:
+                secs[i - 1] += time.perf_counter() - t0
+            dg.dg_state_to_prim(c, q, prim)
+        done += n
+        pb = states[0][3][:, 4, :][emap_big]
+        den += float((Js[:, None] * pb * pb).sum())
+        for i in range(len(runs)):
+            d = states[i + 1][3][:, 4, :][maps[i]] - pb
+            num[i] += float((Js[:, None] * d * d).sum())
+    return ([math.sqrt(x / den) for x in num], [s_ / nsteps for s_ in secs],
+            [c.K for c in runs])
+
+
 def choose_blend(scene, net, window, amp, t_end, dt, blends=(0.25, 0.5, 0.75, 1.0)):
     """The blend weight with the smallest interior reflection error at a
     validation amplitude.  Returns (blend, {blend: error}, char error)."""
@@ -197,7 +242,8 @@ def main():
     ap.add_argument("--eval-amps", default="0.003,0.015")
     ap.add_argument("--val-amp", type=float, default=0.007, help="amplitude / p0 that picks the blend")
     ap.add_argument("--steps", type=int, default=6000)
-    ap.add_argument("--char-scales", default="1.5,2.0", help="char-BC domains for the speedup")
+    ap.add_argument("--char-scales", default="1.25,1.5,2.0",
+                    help="outer boxes (x the small box) run with the characteristic ghost")
     args = ap.parse_args()
     torch = _torch()
     t0 = time.perf_counter()
@@ -230,6 +276,25 @@ def main():
                             "gain": errs[0] / errs[1], "s_per_step_char": secs[0],
                             "s_per_step_learned": secs[1]})
         print(json.dumps(out["eval"][-1]), flush=True)
+    scales = [float(x) for x in args.char_scales.split(",") if x]
+    if scales:
+        a = float(args.eval_amps.split(",")[-1])
+        errs, secs, Ks = char_domains(scene, a * P0, args.t_end, dt, scales)
+        learned = out["eval"][-1]
+        rows = [{"scale": 1.0, "K": out["K_small"], "err_char": learned["err_char"],
+                 "s_per_step": learned["s_per_step_char"]}]
+        rows += [{"scale": sc, "K": K, "err_char": e, "s_per_step": t_}
+                 for sc, e, t_, K in zip(scales, errs, secs, Ks)]
+        out["char_domains"] = rows
+        meet = [r for r in rows if r["err_char"] <= learned["err_learned"]]
+        if meet:
+            r = min(meet, key=lambda r: r["scale"])
+            # DOF-stage updates/s the learned run delivers, counted as the
+            # DOFs the characteristic ghost needs for the same error
+            out["learned_equivalent_speedup"] = r["s_per_step"] / learned["s_per_step_learned"]
+            out["char_scale_needed"] = r["scale"]
+        print(json.dumps({"char_domains": rows,
+                          "speedup": out.get("learned_equivalent_speedup")}), flush=True)
     print(json.dumps(out), flush=True)
 
 
