@@ -130,9 +130,13 @@ def time_single(dg, torch, m, N, form, steps, warmup, kernel_iters):
     torch.cuda.synchronize()
     kernel_s = k0.elapsed_time(k1) * 1e-3 / kernel_iters
     nbytes = stage_bytes(K, Np, True)
+    variant = dg.dg_get_kernel(ctx)
     return {"K": K, "N": N, "Np": Np, "dof": dof, "ms": ms, "wall_s": wall, "t_end": t_end,
             "dt_last": dt_last, "value": dof * 5 * steps / (ms * 1e-3), "kernel_s": kernel_s,
-            "bytes": nbytes, "achieved": nbytes / kernel_s / 1e9, "blocks_per_cu": bpc}
+            "bytes": nbytes, "achieved": nbytes / kernel_s / 1e9, "blocks_per_cu": bpc,
+            "kernel_variant": variant,
+            "kernel": ("stage_kernel" if variant == 0 else "wave_stage_kernel") +
+                      f"<{N},MODE_STAGE>"}
 
 
 def batch_stage_bytes(Ks, Np, members=16):
@@ -187,6 +191,24 @@ def time_batch(dg, torch, steps, warmup, kernel_iters, scale=1.0):
             "t_min": float(t.min()), "t_max": float(t.max())}
 
 
+def time_precision_n5(dg, torch, steps):
+    """The precision workload: the trumpet in the box at 1,165,248 tets,
+    N = 5, FP32 and split-BF16 forms, each with its autotuned launch."""
+    from workloads import trumpet_domain
+    m = trumpet_domain("box", 1_200_000)
+    out = {}
+    for form in ("fp32", "bf16"):
+        o = time_single(dg, torch, m, 5, form, steps, 5, 10)
+        out[form] = {"value": o["value"], "ms_per_step": o["ms"] / steps,
+                     "stage_kernel_ms": o["kernel_s"] * 1e3, "stage_GBs": o["achieved"],
+                     "frac": o["achieved"] / HBM_PEAK_GBS, "kernel": o["kernel"],
+                     "blocks_per_cu": o["blocks_per_cu"]}
+        torch.cuda.empty_cache()
+    out["K"], out["N"], out["steps"] = o["K"], 5, steps
+    out["bf16_speedup"] = out["bf16"]["value"] / out["fp32"]["value"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,9 +218,11 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--form", choices=("fp32", "bf16"), default="fp32",
                     help="form of the headline measurement")
-    ap.add_argument("--also", default="bf16,batch",
-                    help="comma list of extra measurements: bf16, fp32, batch (or empty)")
+    ap.add_argument("--also", default="bf16,batch,n5",
+                    help="comma list of extra measurements: bf16, fp32, batch, n5 (or empty)")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--n5-steps", type=int, default=100,
+                    help="steps per form of the 1.17M-tet N = 5 precision workload")
     ap.add_argument("--kernel-iters", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -224,12 +248,15 @@ def main():
         if name in ("fp32", "bf16") and name != args.form:
             o = time_single(dg, torch, m, N, name, args.steps, args.warmup, args.kernel_iters)
             extra[name] = {"value": o["value"], "ms_per_step": o["ms"] / args.steps,
+                           "kernel": o["kernel"],
                            "speedup_vs_headline": o["value"] / r["value"],
                            "stage_kernel_ms": o["kernel_s"] * 1e3,
                            "stage_GBs": o["achieved"], "frac": o["achieved"] / HBM_PEAK_GBS,
                            "traffic": measured_traffic(name, K)}
         elif name == "batch":
             extra["batch"] = time_batch(dg, torch, args.batch_steps, 4, 10)
+        elif name == "n5":
+            extra["n5"] = time_precision_n5(dg, torch, args.n5_steps)
     if args.copy_mb:
         n = args.copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -255,12 +282,12 @@ def main():
                                "inflow pulse 0.1 p0, characteristic outflow, slip walls",
                    "K": K, "N": N, "Np": Np, "dof": r["dof"], "form": args.form,
                    "t_end": r["t_end"], "dt_last": r["dt_last"], "wall_s": r["wall_s"],
-                   "blocks_per_cu": r["blocks_per_cu"]},
+                   "blocks_per_cu": r["blocks_per_cu"], "kernel_variant": r["kernel_variant"]},
         "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
                                      "copy-calibrated)",
-                     "kernel": f"stage_kernel<{N},MODE_STAGE>", "kernel_ms": r["kernel_s"] * 1e3,
+                     "kernel": r["kernel"], "kernel_ms": r["kernel_s"] * 1e3,
                      "bytes_per_launch": r["bytes"]},
         "forms": extra,
     }

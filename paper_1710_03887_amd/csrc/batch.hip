@@ -37,7 +37,13 @@ struct BShape {
   static constexpr int MT = MP / 16;
   static constexpr int AS = (MP % 32 == 16) ? MP : MP + 16;
   static constexpr int tabBytes = NF + 96 * Nfp + Np;
-  static constexpr int total = KT * AS + (tabBytes + 15) / 16 * 4;  // floats
+  static constexpr int total = KT * AS + (tabBytes + 15) / 16 * 4;  // floats: operator, tables
+  static constexpr int slot = 5 * Np * kMembers;                     // one element's state
+  // each wavefront stages its element's state in LDS when a block of
+  // `waves` wavefronts still fits in the 160 KB of a CU
+  static constexpr bool staged(int waves) { return (total + waves * slot) * 4 <= 160 * 1024; }
+  static constexpr int lds_floats(int waves) { return total + (staged(waves) ? waves * slot : 0); }
+  static_assert(slot % 4 == 0, "state block is whole 16-byte chunks");
 };
 
 template <class T>
@@ -95,12 +101,26 @@ __device__ __forceinline__ size_t qidx(int64_t k, int v, int node, int e, int Np
   return ((size_t(k) * 5 + v) * Np + node) * kMembers + e;
 }
 
+// LDS accesses of one wavefront are performed in order, but the compiler
+// reasons per lane; the fences and the convergent wave barrier make a hand-off
+// of LDS data between lanes explicit (no instruction on gfx950).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef __attribute__((address_space(1))) void* gvoid_ptr_t;
+
 template <int N, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void batch_stage_kernel(BatchLaunch L, float a_rk,
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2))) void batch_stage_kernel(BatchLaunch L, float a_rk,
                                                                  float b_rk, double c_rk,
                                                                  int parity, int rate_out) {
   using S = BShape<N>;
   constexpr int Np = S::Np, Nfp = S::Nfp, MT = S::MT, AS = S::AS;
+  constexpr bool STAGE = S::staged(WAVES);
+  constexpr int QF = (Nfp + 3) / 4;  // face-node quads per face (the last padded)
   extern __shared__ float lds[];
   float* sA = lds;
   uint8_t* sFm = reinterpret_cast<uint8_t*>(lds + S::KT * AS);
@@ -111,6 +131,8 @@ __global__ __launch_bounds__(64 * WAVES) void batch_stage_kernel(BatchLaunch L, 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int e = lane & 15, g = lane >> 4;
   const bool member = e < L.members;
+  // this wavefront's copy of its element's state [5][Np][16] (staged form)
+  float* sQ = lds + S::total + wave * S::slot;
 
   for (int i = tid; i < S::KT * AS; i += 64 * WAVES) sA[i] = L.Aop[i];
   for (int i = tid; i < S::NF; i += 64 * WAVES) sFm[i] = L.fmask[i];
@@ -157,6 +179,32 @@ __global__ __launch_bounds__(64 * WAVES) void batch_stage_kernel(BatchLaunch L, 
       next_first = gi + 1 < L.ngeom ? geom(L, gi + 1).first : INT64_MAX;
     }
     const int64_t k = item - first;
+    const gfloat* qk = qi + size_t(k) * 5 * Np * kMembers;
+    // lane indices the compiler must treat as new each element: otherwise it
+    // hoists every lane-dependent address and mask out of the element loop
+    // and keeps them all live (spilling)
+    int lane_t = lane;
+    asm volatile("" : "+v"(lane_t));
+    const int e = lane_t & 15, g = lane_t >> 4;
+    const bool member = e < L.members;
+
+    // own state: staged into LDS by asynchronous copies, or read from HBM
+    if constexpr (STAGE) {
+      wave_sync();                                  // every lane is done with the slot
+      __builtin_amdgcn_s_waitcnt(0xc07f);           // and its LDS reads have returned
+      constexpr int n4 = S::slot / 4;
+#pragma unroll
+      for (int j = 0; j < (n4 + 63) / 64; ++j) {
+        const int i4 = j * 64 + lane;
+        if (i4 < n4)
+          __builtin_amdgcn_global_load_lds((gvoid_ptr_t)(qk + 4 * i4), (lds_ptr_t)(sQ + j * 256),
+                                           16, 0, 0);
+      }
+    }
+    auto own = [&](int v, int node) __attribute__((always_inline)) -> float {
+      if constexpr (STAGE) return sQ[(v * Np + node) * kMembers + e];
+      else return qk[(v * Np + node) * kMembers + e];
+    };
 
     float gm[9], nx[4], ny[4], nz[4], fs[4];
     int nbr[4], finf[4];
@@ -172,35 +220,30 @@ __global__ __launch_bounds__(64 * WAVES) void batch_stage_kernel(BatchLaunch L, 
       finf[f] = finfo[k * 4 + f];
     }
 
-    // pass 1: Lax-Friedrichs speed per face and member
-    float lam[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int fq = 0; fq < S::NFQ; ++fq) {
-      const int i = 4 * fq + g, f = i / Nfp, ii = i - f * Nfp;
-      const float n[3] = {pick4b(nx, f), pick4b(ny, f), pick4b(nz, f)};
-      const int node = sFm[i], nb = pick4b(nbr, f);
-      float qm[5], qp[5];
+    // exterior traces of face f, lane (g, e) taking face nodes 4q + g of
+    // member e; branch-free: boundary faces load the element's own trace and
+    // discard it
+    auto gather = [&](int f, float (&t)[QF][5]) __attribute__((always_inline)) {
+      const int nb = pick4b(nbr, f), inf = pick4b(finf, f);
+      const bool inner = nb >= 0;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) qm[v] = member ? qi[qidx(k, v, node, e, Np)] : 0.0f;
-      Prim wm;
-      primitive(P, qm, wm);
-      if (nb >= 0) {
-        const int inf = pick4b(finf, f);
-        const int n2 = sNN[((f * 4 + (inf & 3)) * 6 + (inf >> 2)) * Nfp + ii];
+      for (int q = 0; q < QF; ++q) {
+        const int ii = min(4 * q + g, Nfp - 1);
+        const int n2 = inner ? sNN[((f * 4 + (inf & 3)) * 6 + (inf >> 2)) * Nfp + ii]
+                             : sFm[f * Nfp + ii];
+        const gfloat* src = (inner ? qi + size_t(nb) * 5 * Np * kMembers : qk) + n2 * kMembers + e;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qp[v] = member ? qi[qidx(nb, v, n2, e, Np)] : 0.0f;
-      } else {
-        ghost(P, -nb, qm, wm, n, pin, qp);
+        for (int v = 0; v < 5; ++v) {
+          const float val = src[v * Np * kMembers];
+          t[q][v] = (inner && member) ? val : 0.0f;
+        }
       }
-      Prim wp;
-      primitive(P, qp, wp);
-      const float sp = fmaxf(normal_speed(P, wm, n), normal_speed(P, wp, n));
-#pragma unroll
-      for (int ff = 0; ff < 4; ++ff) lam[ff] = (ff == f) ? fmaxf(lam[ff], sp) : lam[ff];
-    }
-#pragma unroll
-    for (int ff = 0; ff < 4; ++ff) {
-      lam[ff] = fmaxf(lam[ff], __shfl_xor(lam[ff], 16));
-      lam[ff] = fmaxf(lam[ff], __shfl_xor(lam[ff], 32));
+    };
+    float trn[QF][5];
+    gather(0, trn);
+    if constexpr (STAGE) {
+      __builtin_amdgcn_s_waitcnt(0);   // the staged state (and face 0's traces) have landed
+      wave_sync();
     }
 
     floatx4 acc[5][MT];
@@ -210,13 +253,14 @@ __global__ __launch_bounds__(64 * WAVES) void batch_stage_kernel(BatchLaunch L, 
       for (int mt = 0; mt < MT; ++mt) acc[v][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     // volume
+#pragma unroll 1
     for (int nq = 0; nq < S::NNQ; ++nq) {
       const int j = 4 * nq + g;
       float F[3][5];
       if (j < Np && member) {
         float q[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) q[v] = qi[qidx(k, v, j, e, Np)];
+        for (int v = 0; v < 5; ++v) q[v] = own(v, j);
         Prim w;
         primitive(P, q, w);
 #pragma unroll
@@ -241,43 +285,72 @@ __global__ __launch_bounds__(64 * WAVES) void batch_stage_kernel(BatchLaunch L, 
         }
     }
 
-    // surface
-    for (int fq = 0; fq < S::NFQ; ++fq) {
-      const int i = 4 * fq + g, f = i / Nfp, ii = i - f * Nfp;
+    // faces one at a time, the next face's traces in flight meanwhile: the
+    // face's Lax-Friedrichs speed per member (max over its nodes and both
+    // sides, reduced over the four lane groups), then the jump
+    // Fscale/2 [n.(F- - F+) - lambda (q- - q+)] against the LIFT rows
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+      float trc[QF][5];
+#pragma unroll
+      for (int q = 0; q < QF; ++q)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) trc[q][v] = trn[q][v];
+      if (f < 3) gather(f + 1, trn);
       const float n[3] = {pick4b(nx, f), pick4b(ny, f), pick4b(nz, f)};
-      const int node = sFm[i], nb = pick4b(nbr, f);
-      float qm[5], qp[5], dF[5];
+      const int nb = pick4b(nbr, f);
+      // the face's traces on both sides (recomputed in the two sub-passes
+      // rather than kept alive across them)
+      auto sides = [&](int q, float (&qm)[5], Prim& wm, float (&qp)[5], Prim& wp)
+          __attribute__((always_inline)) {
+        const int node = sFm[f * Nfp + min(4 * q + g, Nfp - 1)];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) qm[v] = member ? qi[qidx(k, v, node, e, Np)] : 0.0f;
-      Prim wm;
-      primitive(P, qm, wm);
-      if (nb >= 0) {
-        const int inf = pick4b(finf, f);
-        const int n2 = sNN[((f * 4 + (inf & 3)) * 6 + (inf >> 2)) * Nfp + ii];
+        for (int v = 0; v < 5; ++v) qm[v] = member ? own(v, node) : 0.0f;
+        primitive(P, qm, wm);
+        if (nb >= 0) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qp[v] = member ? qi[qidx(nb, v, n2, e, Np)] : 0.0f;
-      } else {
-        ghost(P, -nb, qm, wm, n, pin, qp);
+          for (int v = 0; v < 5; ++v) qp[v] = trc[q][v];
+        } else {
+          ghost(P, -nb, qm, wm, n, pin, qp);
+        }
+        primitive(P, qp, wp);
+      };
+      float lam = 0.0f;
+#pragma unroll
+      for (int q = 0; q < QF; ++q) {
+        float qm[5], qp[5];
+        Prim wm, wp;
+        sides(q, qm, wm, qp, wp);
+        const float sp = fmaxf(normal_speed(P, wm, n), normal_speed(P, wp, n));
+        if (4 * q + g < Nfp) lam = fmaxf(lam, sp);
       }
-      Prim wp;
-      primitive(P, qp, wp);
-      float fm[5], fp[5];
-      normal_flux(P, wm, n, fm);
-      normal_flux(P, wp, n, fp);
-      const float l = pick4b(lam, f);
+      lam = fmaxf(lam, __shfl_xor(lam, 16));
+      lam = fmaxf(lam, __shfl_xor(lam, 32));
       const float hs = member ? 0.5f * pick4b(fs, f) : 0.0f;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) dF[v] = hs * ((fm[v] - fp[v]) - l * (qm[v] - qp[v]));
+      for (int q = 0; q < QF; ++q) {
+        const int ii = 4 * q + g;
+        float qm[5], qp[5], fm[5], fp[5], dF[5];
+        Prim wm, wp;
+        sides(q, qm, wm, qp, wp);
+        normal_flux(P, wm, n, fm);
+        normal_flux(P, wp, n, fp);
+        const float h = ii < Nfp ? hs : 0.0f;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const float av = sA[(S::KV + i) * AS + mt * 16 + e];
+        for (int v = 0; v < 5; ++v) dF[v] = h * ((fm[v] - fp[v]) - lam * (qm[v] - qp[v]));
+        const int row = S::KV + f * Nfp + min(ii, Nfp - 1);
 #pragma unroll
-        for (int v = 0; v < 5; ++v)
-          acc[v][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, dF[v], acc[v][mt], 0, 0, 0);
+        for (int mt = 0; mt < MT; ++mt) {
+          const float av = sA[row * AS + mt * 16 + e];
+#pragma unroll
+          for (int v = 0; v < 5; ++v)
+            acc[v][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, dF[v], acc[v][mt], 0, 0, 0);
+        }
       }
     }
 
-    // epilogue: lane holds nodes mt*16 + 4g + r of member e, all variables
+    // epilogue: lane holds nodes mt*16 + 4g + r of member e, all variables;
+    // the residuals are loaded together first
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -288,10 +361,9 @@ __global__ __launch_bounds__(64 * WAVES) void batch_stage_kernel(BatchLaunch L, 
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           const size_t gx = qidx(k, v, node, e, Np);
-          float rr = dt * acc[v][mt][r];
-          if (a_rk != 0.0f) rr += a_rk * res[gx];
+          const float rr = dt * acc[v][mt][r] + (a_rk != 0.0f ? a_rk * res[gx] : 0.0f);
           res[gx] = rr;
-          qn[v] = qi[gx] + b_rk * rr;
+          qn[v] = own(v, node) + b_rk * rr;
           qo[gx] = qn[v];
         }
         if (rate_out) {
@@ -384,7 +456,7 @@ __global__ void batch_advance_kernel(BatchLaunch L) {
 
 template <int N, int W>
 hipError_t prep(int* bpc) {
-  const int lds = int(BShape<N>::total * sizeof(float));
+  const int lds = int(BShape<N>::lds_floats(W) * sizeof(float));
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_stage_kernel<N, W>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
@@ -411,7 +483,7 @@ void launch_w(const BatchLaunch& L, float a, float b, double c, int parity, int 
               hipStream_t s) {
   const int64_t want = (L.total + W - 1) / W;
   const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(L.num_cu) * L.blocks_per_cu)));
-  const size_t lds = size_t(BShape<N>::total) * sizeof(float);
+  const size_t lds = size_t(BShape<N>::lds_floats(W)) * sizeof(float);
   batch_stage_kernel<N, W><<<blocks, 64 * W, lds, s>>>(L, a, b, c, parity, rate_out);
 }
 

@@ -202,6 +202,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   float rate_best = 0.0f;   // time-step reduction over this block's tiles
   unsigned rate_bad = 0u;
   for (int64_t tile = c0 + jb; tile < c1; tile += Gx) {
+    // at N >= 5, thread indices the compiler must treat as new each tile:
+    // otherwise it hoists every lane-dependent address out of the tile loop
+    // and keeps them all live (spilling); at lower orders the hoisting fits
+    // in registers and is the faster schedule
+    int tid_t = tid;
+    if constexpr (N >= 5) asm volatile("" : "+v"(tid_t));
+    const int lane = tid_t & 63, e = lane & 15, g = lane >> 4;
     const int64_t k0 = tile * kTileE;
     const int ne = int(min<int64_t>(kTileE, m.K - k0));
     const bool valid = e < ne;
@@ -210,7 +217,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 
     // A. asynchronous loads: exterior traces (offsets precomputed), then the
     // state and residual tiles and the FP64 geometry
-    if (tid < kTileE * 4) sL[tid] = 0u;
+    if (tid_t < kTileE * 4) sL[tid_t] = 0u;
 #pragma unroll
     for (int kq = 0; kq < kFQ; ++kq) {
       const int fq = w + kWaves * kq;
@@ -250,21 +257,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                                          16, 0, 0);
       }
     } else {
-      for (int i = tid; i < kTileE * ST; i += kThreads) {
+      for (int i = tid_t; i < kTileE * ST; i += kThreads) {
         sQ[i] = (i < ne * ST) ? qg[i] : 0.0f;
         if (want_res) sR[i] = (i < ne * ST) ? res[k0 * ST + i] : 0.0f;
       }
       double* gd = reinterpret_cast<double*>(lds + S::oG);
-      for (int i = tid; i < kTileE * 9; i += kThreads) gd[i] = (i < ne * 9) ? m.vgeo[k0 * 9 + i] : 0.0;
-      for (int i = tid; i < kTileE * 16; i += kThreads)
+      for (int i = tid_t; i < kTileE * 9; i += kThreads) gd[i] = (i < ne * 9) ? m.vgeo[k0 * 9 + i] : 0.0;
+      for (int i = tid_t; i < kTileE * 16; i += kThreads)
         gd[kTileE * 9 + i] = (i < ne * 16) ? m.sgeo[k0 * 16 + i] : 0.0;
     }
     load_conn(tile + Gx, nbN, fiN);  // next tile's connectivity, in flight meanwhile
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     // geometry to FP32 with padded rows (avoids 16-way bank conflicts)
-    if (tid < kTileE * 16) sFg[(tid >> 4) * 17 + (tid & 15)] = float(sSg[tid]);
-    if (tid < kTileE * 9) sMg[tid] = float(sVg[tid]);
+    if (tid_t < kTileE * 16) sFg[(tid_t >> 4) * 17 + (tid_t & 15)] = float(sSg[tid_t]);
+    if (tid_t < kTileE * 9) sMg[tid_t] = float(sVg[tid_t]);
     gather_offsets(tile + Gx);
     __syncthreads();
 
@@ -456,9 +463,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       bool okv[kOut];
 #pragma unroll
       for (int i = 0; i < kOut; ++i) {
-        const int o = min(tid + i * kThreads, kTileE * MP - 1);
+        const int o = min(tid_t + i * kThreads, kTileE * MP - 1);
         const int eo = o / MP, node = o - eo * MP;
-        okv[i] = (tid + i * kThreads < kTileE * MP) && node < Np && eo < ne;
+        okv[i] = (tid_t + i * kThreads < kTileE * MP) && node < Np && eo < ne;
         const int nd = node < Np ? node : Np - 1;
         float acc_s = 0.0f;
 #pragma unroll
@@ -479,7 +486,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
           res[gidx[i]] = rr;
           q_out[gidx[i]] = qn;
           if (rate_out) {  // same thread, same element/variable/node: in place
-            const int o = tid + i * kThreads;
+            const int o = tid_t + i * kThreads;
             const int eo = o / MP, node = o - eo * MP;
             sQ[eo * ST + v * Np + node] = qn;
           }
@@ -491,7 +498,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     // max over face nodes of (N+1)^2/2 Fscale (|u| + c); non-physical states flagged
     if (MODE == MODE_STAGE && rate_out) {
       __syncthreads();
-      for (int it = tid; it < kTileE * S::NF; it += kThreads) {
+      for (int it = tid_t; it < kTileE * S::NF; it += kThreads) {
         const int eo = it / S::NF, i = it - eo * S::NF, f = i / Nfp;
         if (eo >= ne) continue;
         const int node = sFm[i];

@@ -6,6 +6,8 @@ import paper_1710_03887_amd as dg
 from oracle import euler
 from oracle.mesh import Mesh
 from oracle.operators import RefElement
+from oracle.mesh import FACE_VERTS as _FACE_VERTS
+from workloads import BC_INTERIOR as _BC_INTERIOR, BC_OUTFLOW_CHAR as _BC_OUTFLOW_CHAR
 
 _REFS = {}
 
@@ -65,4 +67,47 @@ def rel_l2(mesh, a, b):
     from oracle.norms import l2
     num = sum(l2(mesh, (a - b)[:, v]) ** 2 for v in range(a.shape[1]))
     den = sum(l2(mesh, b[:, v]) ** 2 for v in range(b.shape[1]))
+    return float(np.sqrt(num / den))
+
+
+# ---- element samples of large meshes ------------------------------------------
+
+def face_keys(EToV):
+    f = np.sort(EToV[:, np.array(_FACE_VERTS)], axis=2).astype(np.int64)   # [K, 4, 3]
+    assert f.max() < (1 << 21)
+    return (f[..., 0] << 42) | (f[..., 1] << 21) | f[..., 2]
+
+
+def neighbour_patch(m, sample, keys):
+    """Sample elements plus every element sharing a face with one of them;
+    faces left unmatched inside the patch get the characteristic tag (they
+    bound neighbours only, never a sampled element)."""
+    touch = np.isin(keys, keys[sample].ravel()).any(axis=1)
+    idx = np.union1d(sample, np.nonzero(touch)[0])
+    bc = m["bc"][idx].copy()
+    pk = keys[idx]
+    uniq, counts = np.unique(pk.ravel(), return_counts=True)
+    single = np.isin(pk, uniq[counts == 1])
+    loose = single & (bc == _BC_INTERIOR)
+    assert not np.isin(idx[np.nonzero(loose)[0]], sample).any()
+    bc[loose] = _BC_OUTFLOW_CHAR
+    return idx, {"xyz": m["xyz"][idx], "EToV": m["EToV"][idx], "bc": bc}
+
+
+def oriented_nodes(xyz, lam):
+    """Nodal coordinates [K, Np, 3] with the oracle's orientation rule
+    (negatively oriented elements swap local vertices 1 and 2)."""
+    e = xyz[:, 1:4] - xyz[:, 0:1]
+    neg = np.einsum("kd,kd->k", np.cross(e[:, 0], e[:, 1]), e[:, 2]) < 0
+    xyz = xyz.copy()
+    xyz[neg] = xyz[neg][:, [0, 2, 1, 3]]
+    return np.einsum("iv,kvd->kid", lam, xyz)
+
+
+def rel_l2_rows(mesh, rows, a, b):
+    """rel_l2 restricted to the elements `rows` of mesh (a, b: [len(rows), 5, Np])."""
+    M, J = mesh.ref.M, mesh.J[rows]
+    num = sum(np.sum(J * np.einsum("ki,ij,kj->k", a[:, v] - b[:, v], M, a[:, v] - b[:, v]))
+              for v in range(5))
+    den = sum(np.sum(J * np.einsum("ki,ij,kj->k", b[:, v], M, b[:, v])) for v in range(5))
     return float(np.sqrt(num / den))
