@@ -114,7 +114,7 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef __attribute__((address_space(1))) void* gvoid_ptr_t;
 
 template <int N, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2))) void batch_stage_kernel(BatchLaunch L, float a_rk,
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(3))) void batch_stage_kernel(BatchLaunch L, float a_rk,
                                                                  float b_rk, double c_rk,
                                                                  int parity, int rate_out) {
   using S = BShape<N>;
