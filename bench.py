@@ -209,6 +209,53 @@ def time_precision_n5(dg, torch, steps):
     return out
 
 
+# stand-ins for the paper's sensors (Section 3, Table 2) placed by their
+# relation to the bell plane (x = 1) and to the outer boundary of this box
+# (x = 1.8, y = 1), a hair off the z = 0 mesh plane: 1 cm in front of the bell
+# edge near the top wall, 2 cm and 1 cm before the far wall on the axis,
+# midway up in front of the bell, and inside the bore near the mouthpiece
+SENSORS = ((1.01, 0.99, 0.003), (1.78, 0.0, 0.003), (1.79, 0.0, 0.003), (1.29, 0.57, 0.003),
+           (0.01, 0.0, 0.003))
+
+
+def time_probes(dg, torch, m, steps=200):
+    """Recording the sensors every step on the c2 trumpet (fixed dt) against
+    the same run without recording, and the spectra of the recorded series."""
+    amp, alpha, p0 = 0.1 / 1.4, 2 * np.pi * 565.0 / 343.0, 1.0 / 1.4
+    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], 4, gamma=1.4, rho0=1.0, p0=p0,
+                           inflow_amp=amp, inflow_alpha=alpha)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    q = torch.zeros((ctx.K, 5, ctx.Np), dtype=torch.float32, device=dev)
+    res = torch.zeros_like(q)
+    dg.dg_autotune(ctx, q, res, None, stream=stream)
+    dg.dg_probe_setup(ctx, SENSORS)
+    dt = dg.dg_stable_dt(ctx, q, 0.5, stream=stream)
+    series = torch.empty((steps, len(SENSORS)), dtype=torch.float32, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    dg.dg_run_fixed(ctx, q, res, 4, dt, 0.0, stream=stream)
+    dg.dg_run_probes(ctx, q, res, 4, dt, 0.0, series[:4], stream=stream)
+    q.zero_(); res.zero_()
+    ev[0].record(stream)
+    t = dg.dg_run_fixed(ctx, q, res, steps, dt, 0.0, stream=stream)
+    ev[1].record(stream)
+    q.zero_(); res.zero_()
+    ev[2].record(stream)
+    t = dg.dg_run_probes(ctx, q, res, steps, dt, 0.0, series, stream=stream)
+    ev[3].record(stream)
+    db = torch.empty((len(SENSORS), steps // 2 + 1), dtype=torch.float32, device=dev)
+    ev[4].record(stream)
+    # dB re 20 micropascal, with p0 standing for one atmosphere (101,325 Pa)
+    dg.dg_spectrum(series, 2e-5 / 101325.0 * p0, db, stream=stream)
+    ev[5].record(stream)
+    torch.cuda.synchronize()
+    plain, rec = ev[0].elapsed_time(ev[1]) / steps, ev[2].elapsed_time(ev[3]) / steps
+    return {"K": ctx.K, "N": 4, "sensors": len(SENSORS), "steps": steps, "dt": dt, "t_end": t,
+            "ms_per_step_plain": plain, "ms_per_step_recording": rec,
+            "recording_overhead": rec / plain - 1.0, "spectrum_ms": ev[4].elapsed_time(ev[5]),
+            "max_abs_p_prime": float(series.abs().max())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,8 +265,9 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--form", choices=("fp32", "bf16"), default="fp32",
                     help="form of the headline measurement")
-    ap.add_argument("--also", default="bf16,batch,n5",
-                    help="comma list of extra measurements: bf16, fp32, batch, n5 (or empty)")
+    ap.add_argument("--also", default="bf16,batch,n5,probes",
+                    help="comma list of extra measurements: bf16, fp32, batch, n5, probes "
+                         "(or empty)")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--n5-steps", type=int, default=100,
                     help="steps per form of the 1.17M-tet N = 5 precision workload")
@@ -257,6 +305,8 @@ def main():
             extra["batch"] = time_batch(dg, torch, args.batch_steps, 4, 10)
         elif name == "n5":
             extra["n5"] = time_precision_n5(dg, torch, args.n5_steps)
+        elif name == "probes":
+            extra["probes"] = time_probes(dg, torch, m)
     if args.copy_mb:
         n = args.copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

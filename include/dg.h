@@ -362,6 +362,51 @@ int64_t dg_learned_faces(const dg_ctx* ctx, int64_t* faces);
 int dg_sample_traces(dg_ctx* ctx, const float* q, const int64_t* faces, int64_t nf, double norm,
                      float* X, float* Y, void* stream);
 
+/* ---- pressure probes and spectra -----------------------------------------
+ * Section 3 samples the pressure of each run at sensor points inside and
+ * around the instrument and compares the frequency content of those signals
+ * (amplitude spectra in dB) between domains.  A probe evaluates the
+ * numerical solution itself at a point: the nodal polynomial of the element
+ * containing the point, interpolated in the conserved perturbation q', then
+ * p - p0 from it (Eq. 2). */
+
+/* Locate n points (host double [n][3], physical coordinates) in the mesh
+ * and keep them, with their nodal interpolation weights, as the context's
+ * probe set (replacing any previous one).  A point on a face shared by two
+ * elements belongs to the element whose smallest barycentric coordinate there
+ * is largest (the first such element on ties).  elements_out (host int64
+ * [n]) receives each point's element and weights_out (host double [n][Np])
+ * its interpolation weights w (value at the point = sum_i w[i] u[node i], in
+ * the library's node order); either may be NULL.  On a host-only context
+ * the points are located and weighed but no probe set is kept.
+ * Synchronous.  Errors: DG_EINVAL for n outside 1..2^20 or a point outside
+ * the mesh (tolerance 1e-9 in barycentric coordinates), DG_ENOMEM. */
+int dg_probe_setup(dg_ctx* ctx, const double* xyz, int32_t n, int64_t* elements_out,
+                   double* weights_out);
+
+/* p - p0 at every probe of state q (device, the state layout) into out
+ * (device FP32 [n]).  Asynchronous.  DG_EINVAL without probes. */
+int dg_probe_sample(dg_ctx* ctx, const float* q, float* out, void* stream);
+
+/* dg_run_fixed that also records, after every step j (0-based), p - p0 at
+ * every probe into series[j][p] (device FP32 [nsteps][n], caller-owned): a
+ * uniformly sampled signal with spacing dt.  Same ownership, synchronization
+ * and errors as dg_run_fixed; DG_EINVAL without probes or with a null
+ * series. */
+int dg_run_probes(dg_ctx* ctx, float* q, float* res, int64_t nsteps, double dt, double* t_inout,
+                  float* series, void* stream);
+
+/* One-sided amplitude spectra of n_signals real signals of n_samples
+ * uniformly spaced samples, series[j][s] (device FP32, the layout
+ * dg_run_probes writes): db[s][k] (device FP32 [n_signals][n_samples/2 + 1])
+ * = 20 log10(A_k / p_ref) with A_k = 2 |X_k| / n_samples (|X_k| / n_samples
+ * at k = 0 and k = n_samples/2), X_k = sum_j x_j exp(-2 pi i k j / n_samples),
+ * floored at -600 dB.  Bin k is the frequency k / (n_samples dt).  No
+ * context; errors through dg_last_error(NULL).  Asynchronous.  DG_EINVAL for
+ * n_samples < 2, n_signals outside 1..65535 or p_ref <= 0. */
+int dg_spectrum(const float* series, int64_t n_samples, int32_t n_signals, double p_ref,
+                float* db, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,6 +86,10 @@ _SIGS = {
     "dg_set_learned_bc": (ctypes.c_int, [_vp, _vp, _f64, _f64, _f64, _f64]),
     "dg_learned_faces": (_i64, [_vp, _vp]),
     "dg_sample_traces": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, _vp, _vp, _vp]),
+    "dg_probe_setup": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
+    "dg_probe_sample": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "dg_run_probes": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, ctypes.POINTER(_f64), _vp, _vp]),
+    "dg_spectrum": (ctypes.c_int, [_vp, _i64, _i32, _f64, _vp, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -416,6 +420,60 @@ def dg_run_fixed(ctx, q, res, nsteps, dt, t=0.0, stream=None):
     _check(_lib.dg_run_fixed(ctx.handle, _ptr(q), _ptr(res), int(nsteps), float(dt),
                              ctypes.byref(tt), _stream(stream)), ctx.handle)
     return tt.value
+
+
+# ---- pressure probes and spectra -----------------------------------------------------
+def _check_device_f32(x, shape, name):
+    if x is None or tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}")
+    if str(getattr(x, "dtype", "")) != "torch.float32" or not getattr(x, "is_cuda", False):
+        raise ValueError(f"{name} must be a float32 device tensor")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def dg_probe_setup(ctx, xyz, weights=False):
+    """Locate points (array [n, 3]) and keep them as the probe set; returns
+    the element index of each point (numpy int64 [n]) and, with weights,
+    also their interpolation weights (numpy float64 [n, Np])."""
+    pts = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+    elems = np.empty(len(pts), dtype=np.int64)
+    w = np.empty((len(pts), ctx.Np), dtype=np.float64) if weights else None
+    _check(_lib.dg_probe_setup(ctx.handle, _ptr(pts), int(len(pts)), _ptr(elems), _ptr(w)),
+           ctx.handle)
+    ctx.n_probes = len(pts)
+    return (elems, w) if weights else elems
+
+
+def dg_probe_sample(ctx, q, out, stream=None):
+    """p - p0 at every probe of state q into out (device float32 [n])."""
+    _check_state(ctx, q, "q")
+    _check_device_f32(out, (getattr(ctx, "n_probes", 0),), "out")
+    _check(_lib.dg_probe_sample(ctx.handle, _ptr(q), _ptr(out), _stream(stream)), ctx.handle)
+
+
+def dg_run_probes(ctx, q, res, nsteps, dt, t=0.0, series=None, stream=None):
+    """dg_run with a fixed dt that records p - p0 at every probe after every
+    step into series (device float32 [nsteps, n]); returns the end time."""
+    _check_state(ctx, q, "q")
+    _check_state(ctx, res, "res")
+    _check_device_f32(series, (int(nsteps), getattr(ctx, "n_probes", 0)), "series")
+    tt = _f64(t)
+    _check(_lib.dg_run_probes(ctx.handle, _ptr(q), _ptr(res), int(nsteps), float(dt),
+                              ctypes.byref(tt), _ptr(series), _stream(stream)), ctx.handle)
+    return tt.value
+
+
+def dg_spectrum(series, p_ref, db, stream=None):
+    """Amplitude spectra in dB of the columns of series (device float32
+    [n_samples, n_signals]) into db (device float32 [n_signals, n_samples//2 + 1])."""
+    if series is None or series.dim() != 2:
+        raise ValueError("series must be a 2-D device tensor")
+    n, ns = series.shape
+    _check_device_f32(series, (n, ns), "series")
+    _check_device_f32(db, (ns, n // 2 + 1), "db")
+    _check(_lib.dg_spectrum(_ptr(series), int(n), int(ns), float(p_ref), _ptr(db),
+                            _stream(stream)), None)
 
 
 # ---- learned boundary closure ------------------------------------------------------

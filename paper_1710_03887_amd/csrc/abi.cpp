@@ -44,9 +44,19 @@ int upload(dg_ctx* c, const T* host, size_t n, T** dev, hipStream_t s) {
   return DG_OK;
 }
 
+void free_probes(dg_ctx* c) {
+  if (c->probe_elem) (void)hipFree(c->probe_elem);
+  if (c->probe_w) (void)hipFree(c->probe_w);
+  if (c->probe_dev) (void)hipFree(c->probe_dev);
+  c->probe_elem = nullptr;
+  c->probe_w = nullptr;
+  c->probe_dev = nullptr;
+  c->probe_host = dg::ProbeSet{};
+}
+
 void free_device(dg_ctx* c) {
-  if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
-  c->two_steps = dg::GraphCache{};
+  drop_graphs(c);
+  free_probes(c);
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -347,8 +357,10 @@ int dg_stable_dt(dg_ctx* c, const float* q, double cfl, double* dt, void* stream
 
 namespace {
 
+// The run loop; with `series`, the probe values of every step are recorded
+// into series[step][probe] (probes set up, nsteps rows).
 int run_impl(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double fixed_dt,
-             double* t_inout, double* dt_last, hipStream_t s) {
+             double* t_inout, double* dt_last, hipStream_t s, float* series = nullptr) {
   c->host_run = dg::RunScalars{};
   c->host_run.t = *t_inout;
   c->host_run.cfl = cfl;
@@ -361,6 +373,14 @@ int run_impl(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double
   hipError_t e = hipMemcpyAsync(c->run, &c->host_run, sizeof(dg::RunScalars),
                                 hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  const int np = c->probe_host.n;
+  if (series) {
+    c->probe_host.series = series;
+    c->probe_host.cap = nsteps;
+    e = hipMemcpyAsync(c->probe_dev, &c->probe_host, sizeof(dg::ProbeSet), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  }
+  dg::GraphCache& gc = series ? c->probe_steps : c->two_steps;
 
   // the first step's CFL rate; every later one comes from the last stage
   // of the step before
@@ -368,9 +388,9 @@ int run_impl(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double
   if (e != hipSuccess) return hip_fail(c, e, "rate launch");
 
   // a graph of two steps (ten stage swaps) leaves the state in q
-  if (nsteps >= 2 && (c->two_steps.q != q || c->two_steps.res != res || !c->two_steps.exec)) {
-    if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
-    c->two_steps = dg::GraphCache{};
+  if (nsteps >= 2 && (gc.q != q || gc.res != res || !gc.exec)) {
+    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+    gc = dg::GraphCache{};
     hipStream_t cs = c->capture_stream;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
@@ -379,6 +399,9 @@ int run_impl(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double
       le = dg::launch_finalize(c->run, cs);
       if (le == hipSuccess) le = enqueue_stages(c, q, res, k == 0, 0.0, 0.0, c->run, cs);
       if (le == hipSuccess) le = dg::launch_advance(c->run, cs);
+      // the step's state is in the partner buffer after the first step, in q after the second
+      if (le == hipSuccess && series)
+        le = dg::launch_probe(c->probe_dev, np, c->dm, k == 0 ? c->qbuf : q, nullptr, c->run, cs);
     }
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
@@ -391,12 +414,12 @@ int run_impl(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
-    c->two_steps.exec = ex;
-    c->two_steps.q = q;
-    c->two_steps.res = res;
+    gc.exec = ex;
+    gc.q = q;
+    gc.res = res;
   }
   for (int64_t k = 0; k + 1 < nsteps; k += 2) {
-    e = hipGraphLaunch(c->two_steps.exec, s);
+    e = hipGraphLaunch(gc.exec, s);
     if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
   }
   if (nsteps % 2 == 1) {
@@ -406,6 +429,7 @@ int run_impl(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double
     if (e == hipSuccess)
       e = hipMemcpyAsync(q, c->qbuf, size_t(c->dm.K) * 5 * c->dm.Np * sizeof(float),
                          hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && series) e = dg::launch_probe(c->probe_dev, np, c->dm, q, nullptr, c->run, s);
     if (e != hipSuccess) return hip_fail(c, e, "single step");
   }
   e = hipMemcpyAsync(&c->host_run, c->run, sizeof(dg::RunScalars), hipMemcpyDeviceToHost, s);
@@ -447,12 +471,84 @@ int dg_set_kernel(dg_ctx* c, int variant) {
   if (variant == 1 && !dg::wave_stage_supported(c->dm.N, c->dm.precision))
     return fail(c, DG_EINVAL, "the wavefront-private stage kernel needs the FP32 form and N <= 4");
   c->dm.variant = variant;
-  if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
-  c->two_steps = dg::GraphCache{};
+  drop_graphs(c);
   return DG_OK;
 }
 
 int dg_get_kernel(const dg_ctx* c) { return c ? c->dm.variant : -1; }
+
+int dg_probe_setup(dg_ctx* c, const double* xyz, int32_t n, int64_t* elements_out,
+                   double* weights_out) {
+  if (!c) return fail(nullptr, DG_EINVAL, "null context");
+  if (!xyz || n < 1 || n > (1 << 20)) return fail(c, DG_EINVAL, "need 1 <= n <= 2^20 points");
+  const int Np = c->ops.Np;
+  std::vector<int64_t> elem(n);
+  std::vector<float> w(size_t(n) * Np);
+  std::vector<double> wd(Np);
+  for (int32_t p = 0; p < n; ++p) {
+    double rst[3];
+    elem[p] = dg::locate_point(c->mesh, xyz + size_t(p) * 3, 1e-9, rst);
+    if (elem[p] < 0) return fail(c, DG_EINVAL, "probe " + std::to_string(p) + " lies outside the mesh");
+    dg::interpolation_weights(c->ops, rst, wd.data());
+    for (int i = 0; i < Np; ++i) w[size_t(p) * Np + i] = float(wd[i]);
+    if (weights_out) std::copy(wd.begin(), wd.end(), weights_out + size_t(p) * Np);
+  }
+  if (elements_out) std::copy(elem.begin(), elem.end(), elements_out);
+  if (c->host_only) return DG_OK;  // located and weighed only
+  drop_graphs(c);
+  free_probes(c);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&c->probe_elem), sizeof(int64_t) * n);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->probe_w), sizeof(float) * w.size());
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->probe_dev), sizeof(dg::ProbeSet));
+  if (e != hipSuccess) {
+    free_probes(c);
+    return fail(c, DG_ENOMEM, "hipMalloc failed");
+  }
+  c->probe_host.n = n;
+  c->probe_host.Np = Np;
+  c->probe_host.elem = c->probe_elem;
+  c->probe_host.w = c->probe_w;
+  e = hipMemcpy(c->probe_elem, elem.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->probe_w, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->probe_dev, &c->probe_host, sizeof(dg::ProbeSet), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_probes(c);
+    return hip_fail(c, e, "probe upload");
+  }
+  return DG_OK;
+}
+
+int dg_probe_sample(dg_ctx* c, const float* q, float* out, void* stream) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (!q || !out) return fail(c, DG_EINVAL, "null argument");
+  if (c->probe_host.n < 1) return fail(c, DG_EINVAL, "no probes set up");
+  const hipError_t e = dg::launch_probe(c->probe_dev, c->probe_host.n, c->dm, q, out, nullptr,
+                                        static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DG_OK : hip_fail(c, e, "probe launch");
+}
+
+int dg_run_probes(dg_ctx* c, float* q, float* res, int64_t nsteps, double dt, double* t_inout,
+                  float* series, void* stream) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (!q || !res || !t_inout || !series) return fail(c, DG_EINVAL, "null argument");
+  if (nsteps < 0 || !(dt > 0.0)) return fail(c, DG_EINVAL, "need nsteps >= 0 and dt > 0");
+  if (c->probe_host.n < 1) return fail(c, DG_EINVAL, "no probes set up");
+  return run_impl(c, q, res, nsteps, 1.0, dt, t_inout, nullptr, static_cast<hipStream_t>(stream),
+                  series);
+}
+
+int dg_spectrum(const float* series, int64_t n_samples, int32_t n_signals, double p_ref, float* db,
+                void* stream) {
+  if (!series || !db) return fail(nullptr, DG_EINVAL, "null argument");
+  if (n_samples < 2 || n_signals < 1 || n_signals > 65535 || !(p_ref > 0.0))
+    return fail(nullptr, DG_EINVAL, "need n_samples >= 2, 1 <= n_signals <= 65535, p_ref > 0");
+  const hipError_t e = dg::launch_spectrum(series, n_samples, n_signals, p_ref, db,
+                                           static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DG_OK : hip_fail(nullptr, e, "spectrum launch");
+}
 
 int dg_set_launch(dg_ctx* c, int blocks_per_cu) {
   int rc = need_device(c);
@@ -460,8 +556,7 @@ int dg_set_launch(dg_ctx* c, int blocks_per_cu) {
   if (blocks_per_cu < 0) return fail(c, DG_EINVAL, "blocks_per_cu must be >= 0");
   c->dm.blocks_per_cu = blocks_per_cu == 0 ? c->max_blocks_per_cu
                                            : std::min(blocks_per_cu, c->max_blocks_per_cu);
-  if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
-  c->two_steps = dg::GraphCache{};
+  drop_graphs(c);
   return DG_OK;
 }
 

@@ -136,8 +136,7 @@ int dg_autotune(dg_ctx* c, const float* q, float* res, const char* cache_path, i
   }
   c->dm.blocks_per_cu = best;
   c->dm.variant = best_v;
-  if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
-  c->two_steps = dg::GraphCache{};
+  drop_graphs(c);
   if (blocks_per_cu) *blocks_per_cu = best;
   return DG_OK;
 }

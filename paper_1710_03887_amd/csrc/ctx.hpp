@@ -11,6 +11,7 @@
 #include "batch.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
+#include "probes.hpp"
 #include "setup.hpp"
 
 namespace dg {
@@ -57,8 +58,22 @@ struct dg_ctx {
   dg::RunScalars host_run{};        // staging for uploads/downloads
   hipStream_t capture_stream = nullptr;
   dg::GraphCache two_steps;
+  dg::GraphCache probe_steps;       // two steps with probe recording
+  dg::ProbeSet probe_host{};        // staging of the device probe set
+  dg::ProbeSet* probe_dev = nullptr;
+  int64_t* probe_elem = nullptr;    // device [n]
+  float* probe_w = nullptr;         // device [n][Np]
   int64_t last_bad = -1;
 };
+
+// Captured step graphs are rebuilt after anything they bake in changes
+// (kernel variant, launch shape, learned closure, probes).
+inline void drop_graphs(dg_ctx* c) {
+  if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
+  c->two_steps = dg::GraphCache{};
+  if (c->probe_steps.exec) (void)hipGraphExecDestroy(c->probe_steps.exec);
+  c->probe_steps = dg::GraphCache{};
+}
 
 struct dg_batch {
   std::string err;

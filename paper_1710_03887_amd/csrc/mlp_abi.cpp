@@ -212,8 +212,7 @@ int dg_set_learned_bc(dg_ctx* c, dg_mlp* m, double norm, double p_lo, double p_h
   c->lbc.phi = float(p_hi);
   c->lbc.blend = float(blend);
   c->dm.lghost = (m && c->lbc.nl > 0) ? c->lbc.ghost : nullptr;
-  if (c->two_steps.exec) (void)hipGraphExecDestroy(c->two_steps.exec);
-  c->two_steps = dg::GraphCache{};
+  drop_graphs(c);
   return DG_OK;
 }
 

@@ -323,6 +323,7 @@ std::string build_reference(int N, RefOps& ops) {
   }
   std::vector<double> Vinv = V;
   if (!invert(Vinv, Np)) return "singular Vandermonde matrix";
+  ops.Vinv = Vinv;
   ops.Dr = matmul(Vr, Vinv, Np, Np, Np);
   ops.Ds = matmul(Vs, Vinv, Np, Np, Np);
   ops.Dt = matmul(Vt, Vinv, Np, Np, Np);
@@ -561,6 +562,46 @@ void neighbour_map(const RefOps& ops, const HostMesh& m, int64_t* out) {
         out[(size_t(k) * 4 + f) * Nfp + i] = v;
       }
     }
+}
+
+int64_t locate_point(const HostMesh& m, const double x[3], double tol, double rst[3]) {
+  int64_t best = -1;
+  double best_min = -1e300;
+  for (int64_t k = 0; k < m.K; ++k) {
+    const double* X = &m.xyz[size_t(k) * 12];
+    const double* G = &m.drst_dx[size_t(k) * 9];
+    const double d[3] = {x[0] - X[0], x[1] - X[1], x[2] - X[2]};
+    // x - v0 = sum_a (1 + r_a)/2 (v_a - v0): (1 + r_a) = G[a] . (x - v0)
+    double l[4];
+    for (int a = 0; a < 3; ++a) l[a + 1] = 0.5 * (G[a * 3] * d[0] + G[a * 3 + 1] * d[1] + G[a * 3 + 2] * d[2]);
+    l[0] = 1.0 - l[1] - l[2] - l[3];
+    const double mn = std::min(std::min(l[0], l[1]), std::min(l[2], l[3]));
+    if (mn > best_min) {
+      best_min = mn;
+      best = k;
+      for (int a = 0; a < 3; ++a) rst[a] = 2.0 * l[a + 1] - 1.0;
+    }
+  }
+  return best_min >= -tol ? best : -1;
+}
+
+void interpolation_weights(const RefOps& ops, const double rst[3], double* w) {
+  const int N = ops.N, Np = ops.Np;
+  std::vector<double> psi(Np);
+  int m = 0;
+  for (int i = 0; i <= N; ++i)
+    for (int j = 0; j <= N - i; ++j)
+      for (int k = 0; k <= N - i - j; ++k, ++m) {
+        double v, vr, vs, vt;
+        basis3(i, j, k, rst[0], rst[1], rst[2], v, vr, vs, vt);
+        psi[m] = v;
+      }
+  // u(x) = sum_m psi_m(x) c_m with c = V^-1 u, so w_i = sum_m psi_m(x) Vinv[m][i]
+  for (int i = 0; i < Np; ++i) {
+    double acc = 0.0;
+    for (int mm = 0; mm < Np; ++mm) acc += psi[mm] * ops.Vinv[size_t(mm) * Np + i];
+    w[i] = acc;
+  }
 }
 
 }  // namespace dg

@@ -18,6 +18,7 @@ struct RefOps {
   // coincides with node i of my face f, when the neighbour's face is f2 and
   // o is the orientation code of the shared vertex triple.
   std::vector<uint8_t> nbr_node;
+  std::vector<double> Vinv;  // [Np][Np] inverse of V[n][m] = psi_m(node n)
 };
 
 struct HostMesh {
@@ -46,5 +47,16 @@ void node_coordinates(const RefOps& ops, const HostMesh& mesh, double* out);
 
 // Neighbour node map [K][4][Nfp] (k'*Np + node, or -1).
 void neighbour_map(const RefOps& ops, const HostMesh& mesh, int64_t* out);
+
+// Element containing the physical point x: the element whose smallest
+// barycentric coordinate at x is largest (first such element on ties), or -1
+// when that coordinate is below -tol (the point lies outside the mesh).
+// rst receives the point's reference coordinates in that element.
+int64_t locate_point(const HostMesh& mesh, const double x[3], double tol, double rst[3]);
+
+// Nodal interpolation weights w[i] = l_i(r, s, t) of the order-N nodal basis
+// at a reference point: the polynomial through nodal values u_i takes the
+// value sum_i w[i] u_i there.
+void interpolation_weights(const RefOps& ops, const double rst[3], double* w);
 
 }  // namespace dg

@@ -1,0 +1,133 @@
+"""Pressure probes and spectra on the GPU against the FP64 oracle
+(oracle/probes.py).
+
+Bars: a probe value is an interpolation of the FP32 state (35 or fewer
+products per variable) followed by the perturbation-form pressure, so it
+carries the state's own FP32 error (relative ~1e-7); the bar is 1e-5 of the
+largest |p'| for one state and 1e-5 relative L2 for a 41-step series (the
+state bar of the solver).  Spectra: the same series in dB, within 1e-3 dB
+on every bin within 100 dB of the strongest one.
+"""
+import numpy as np
+import pytest
+
+import paper_1710_03887_amd as dg
+from oracle import euler, probes, timestep
+from workloads import box_kuhn, trumpet_domain, gaussian_pulse
+from helpers import Pair
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _inside_points(mesh, n, seed):
+    rng = np.random.default_rng(seed)
+    elems = rng.choice(mesh.K, n, replace=False)
+    lam = rng.dirichlet(np.ones(4), size=n) * 0.9 + 0.025
+    lam /= lam.sum(axis=1, keepdims=True)
+    return np.einsum("pa,pad->pd", lam, mesh.xyz[elems])
+
+
+def _state(pair, amp, width, center, flow=0.0):
+    phys = pair.phys
+    prim = gaussian_pulse(pair.mesh.x, amp * phys.p0, width, center, phys.rho0, phys.p0, phys.gamma)
+    prim[..., 2] += flow * np.sin(np.pi * pair.mesh.x[..., 0])
+    return euler.initial_state(prim, phys.gamma)
+
+
+@pytest.mark.parametrize("case", ["box_n3_moving", "trumpet_n4"])
+def test_probe_sample_parity(case):
+    if case == "box_n3_moving":
+        phys = euler.Physics(u0=(0.05, -0.02, 0.01))
+        pair = Pair(box_kuhn(3, jitter=0.05, seed=4), 3, phys)
+        q = _state(pair, 0.1, 0.4, (0.1, 0.0, -0.1), flow=0.03)
+    else:
+        phys = euler.Physics(amp=0.1 / 1.4)
+        pair = Pair(trumpet_domain("box", 3000), 4, phys)
+        q = _state(pair, 0.05, 0.3, (0.9, 0.05, 0.0), flow=0.02)
+    pts = _inside_points(pair.mesh, 30, 7)
+    elem, rst = probes.locate(pair.mesh, pts)
+    p_or = probes.sample(pair.mesh, q, elem, probes.weights(pair.mesh.ref, rst), phys)
+    e_lib = dg.dg_probe_setup(pair.ctx, pts)
+    assert np.array_equal(e_lib, elem)
+    out = torch.full((len(pts),), float("nan"), device="cuda")
+    dg.dg_probe_sample(pair.ctx, pair.to_device(q), out)
+    torch.cuda.synchronize()
+    err = np.abs(out.double().cpu().numpy() - p_or).max() / np.abs(p_or).max()
+    print(f"{case}: probe p' max error {err:.2e} of max |p'|")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("nsteps", [41, 40])
+def test_run_probes_parity_and_consistency(nsteps):
+    phys = euler.Physics()
+    pair = Pair(box_kuhn(4, jitter=0.05, seed=9), 2, phys)
+    q0 = _state(pair, 0.1, 0.25, (0.0, 0.0, 0.0))
+    dt = 0.8 * timestep.stable_dt(pair.mesh, q0, phys, 0.5)
+    pts = _inside_points(pair.mesh, 12, 3)
+    elem, rst = probes.locate(pair.mesh, pts)
+    q_or, t_or, s_or = probes.record(pair.mesh, q0, phys, nsteps, dt, elem,
+                                     probes.weights(pair.mesh.ref, rst))
+    dg.dg_probe_setup(pair.ctx, pts)
+    qd = pair.to_device(q0)
+    res = torch.zeros_like(qd)
+    series = torch.full((nsteps, len(pts)), float("nan"), device="cuda")
+    t = dg.dg_run_probes(pair.ctx, qd, res, nsteps, dt, 0.0, series)
+    torch.cuda.synchronize()
+    s_gpu = series.double().cpu().numpy()
+    err = np.linalg.norm(s_gpu - s_or) / np.linalg.norm(s_or)
+    print(f"{nsteps} steps: probe series rel L2 {err:.2e}")
+    assert abs(t / t_or - 1) < 1e-12 and err < 1e-5
+    # recording does not change the run, and the last row is the final state's probes
+    qf = pair.to_device(q0)
+    rf = torch.zeros_like(qf)
+    dg.dg_run_fixed(pair.ctx, qf, rf, nsteps, dt, 0.0)
+    last = torch.empty(len(pts), device="cuda")
+    dg.dg_probe_sample(pair.ctx, qd, last)
+    torch.cuda.synchronize()
+    assert torch.equal(qf, qd)
+    assert torch.equal(last, series[-1])
+
+
+def test_spectrum_parity_and_closed_form():
+    n = 2000
+    rng = np.random.default_rng(1)
+    j = np.arange(n)
+    x = np.stack([0.37 * np.cos(2 * np.pi * 41 * j / n + 0.3),
+                  np.convolve(rng.standard_normal(n + 20), np.ones(21) / 21, "valid")[:n],
+                  1e-3 * rng.standard_normal(n)], axis=1).astype(np.float32)
+    db_or = probes.spectrum(x.astype(np.float64), 1e-3)
+    xd = torch.tensor(x, device="cuda")
+    db = torch.empty((3, n // 2 + 1), device="cuda")
+    dg.dg_spectrum(xd, 1e-3, db)
+    torch.cuda.synchronize()
+    g = db.double().cpu().numpy()
+    for s in range(3):
+        keep = db_or[s] > db_or[s].max() - 100
+        d = np.abs(g[s, keep] - db_or[s, keep]).max()
+        print(f"signal {s}: max |dB difference| {d:.2e} over {keep.sum()} bins")
+        assert d < 1e-3
+    assert abs(g[0, 41] - 20 * np.log10(0.37 / 1e-3)) < 1e-3   # closed form
+    odd = torch.tensor(x[:1999], device="cuda")                  # odd length
+    db2 = torch.empty((3, 1000), device="cuda")
+    dg.dg_spectrum(odd, 1e-3, db2)
+    torch.cuda.synchronize()
+    ref2 = probes.spectrum(x[:1999].astype(np.float64), 1e-3)
+    keep = ref2 > ref2.max(axis=1, keepdims=True) - 100
+    assert np.abs(db2.double().cpu().numpy()[keep] - ref2[keep]).max() < 1e-3
+
+
+def test_probe_errors():
+    pair = Pair(box_kuhn(1), 2, euler.Physics())
+    q = torch.zeros((pair.ctx.K, 5, pair.ctx.Np), device="cuda")
+    pair.ctx.n_probes = 1
+    with pytest.raises(dg.DGError):
+        dg.dg_probe_sample(pair.ctx, q, torch.empty(1, device="cuda"))
+    with pytest.raises(dg.DGError):
+        dg.dg_run_probes(pair.ctx, q, torch.zeros_like(q), 2, 0.01, 0.0,
+                         torch.empty((2, 1), device="cuda"))
+    with pytest.raises(dg.DGError):
+        dg.dg_probe_setup(pair.ctx, [[2.0, 2.0, 2.0]])
+    with pytest.raises(dg.DGError):
+        dg.dg_spectrum(torch.empty((1, 1), device="cuda"), 1.0, torch.empty((1, 1), device="cuda"))
