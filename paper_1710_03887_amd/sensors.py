@@ -1,0 +1,138 @@
+"""Sensor study of Section 3: the mouthpiece pulse recorded at sensor points
+around the trumpet in several outer domains, and the domains compared
+through the amplitude spectra of those recordings.
+
+Section 3 places the instrument in full domains (Type A: box, sphere, ...)
+and in domains that keep only the region in front of the bell (Type B), runs
+the same pulse in each, and compares the pressure spectra at sensors near the
+bell and near the outer boundary (Table 2 gives each sensor's distance from
+the bell and from the boundary): matching spectra mean the boundary
+treatment let the pulse out without disturbing the solution.  Here the
+domains are the synthetic trumpet domains of this package (box, sphere of
+radius 1.5, half domain), the sensors stand-ins placed by the same relations
+to the bell plane (x = 1) and to this box's walls (x = 1.8, y = 1), and every
+signal is recorded every step by the library's probe kernel inside the
+captured step graph, with one fixed time step shared by all domains so that
+the spectra share their frequency bins.
+
+    python -m paper_1710_03887_amd.sensors [--amps 0.005,0.02] [--t-end 3.0]
+
+Prints one JSON line per domain run and a summary line: per sensor and
+domain the peak |p'| and the spectrum in dB re 20 micropascal (p0 standing
+for one atmosphere) at octave-spaced frequencies, and the mean |dB
+difference| of each domain from the box over the band where the box's
+spectrum lies within 60 dB of its peak.
+"""
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from . import _lib as dg
+
+GAMMA, RHO0, P0 = 1.4, 1.0, 1.0 / 1.4
+ALPHA = 2 * np.pi * 565.0 / 343.0
+HZ = 343.0            # one time unit is 1/343 s (lengths in metres, c0 = 1)
+P_REF = 2e-5 / 101325.0 * P0
+SENSORS = {
+    "sensor 1 (1 cm before the bell edge, 1 cm below the top wall)": (1.01, 0.99, 0.003),
+    "sensor 2 (on axis, 2 cm before the far wall)": (1.78, 0.0, 0.003),
+    "sensor 3 (on axis, 1 cm before the far wall)": (1.79, 0.0, 0.003),
+    "sensor 4 (in front of the bell, 0.57 up)": (1.29, 0.57, 0.003),
+    "bore (1 cm inside the mouthpiece)": (0.01, 0.0, 0.003),
+}
+DOMAINS = (("box", 50_000), ("sphere", 80_000), ("half", 30_000))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def setup(kind, target_K, amp, N=4):
+    from workloads import trumpet_domain
+    torch = _torch()
+    m = trumpet_domain(kind, target_K)
+    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, gamma=GAMMA, rho0=RHO0, p0=P0,
+                           inflow_amp=amp * P0, inflow_alpha=ALPHA)
+    q = torch.zeros((ctx.K, 5, ctx.Np), dtype=torch.float32, device="cuda")
+    res = torch.zeros_like(q)
+    dg.dg_autotune(ctx, q, res)
+    dg.dg_probe_setup(ctx, list(SENSORS.values()))
+    return ctx, q, res
+
+
+def record(ctx, q, res, nsteps, dt, chunk=5000, label=""):
+    """The sensors' p' after every step: device [nsteps, n_sensors]."""
+    torch = _torch()
+    series = torch.empty((nsteps, len(SENSORS)), dtype=torch.float32, device="cuda")
+    t, done, t0 = 0.0, 0, time.perf_counter()
+    while done < nsteps:
+        n = min(chunk, nsteps - done)
+        t = dg.dg_run_probes(ctx, q, res, n, dt, t, series[done:done + n])
+        done += n
+        print(f"{label} step {done}/{nsteps} t={t:.3f} ({time.perf_counter() - t0:.0f} s)",
+              flush=True)
+    return series, t, time.perf_counter() - t0
+
+
+def spectra(series):
+    torch = _torch()
+    n = series.shape[0]
+    db = torch.empty((series.shape[1], n // 2 + 1), dtype=torch.float32, device="cuda")
+    dg.dg_spectrum(series, P_REF, db)
+    return db.double().cpu().numpy()
+
+
+def main():
+    ap = argparse.ArgumentParser(description="sensor spectra of the trumpet pulse per domain")
+    ap.add_argument("--amps", default="0.005,0.02", help="inflow amplitudes / p0")
+    ap.add_argument("--t-end", type=float, default=3.0)
+    ap.add_argument("--N", type=int, default=4)
+    args = ap.parse_args()
+    torch = _torch()
+    names = list(SENSORS)
+    summary = {"sensors": SENSORS, "runs": []}
+    for amp in [float(a) for a in args.amps.split(",") if a]:
+        ctxs = {kind: setup(kind, K, amp, args.N) for kind, K in DOMAINS}
+        dt = 0.9 * min(dg.dg_stable_dt(c, q, 0.5) for c, q, _ in ctxs.values())
+        nsteps = int(math.ceil(args.t_end / dt))
+        freqs = np.arange(nsteps // 2 + 1) / (nsteps * dt) * HZ
+        octaves = [f for f in (62.5, 125, 250, 500, 1000, 2000, 4000, 8000) if f < freqs[-1]]
+        bins = [int(np.argmin(np.abs(freqs - f))) for f in octaves]
+        db, peak = {}, {}
+        for kind, (ctx, q, res) in ctxs.items():
+            s, t, secs = record(ctx, q, res, nsteps, dt, label=f"{kind} {amp}")
+            db[kind] = spectra(s)
+            peak[kind] = s.abs().max(dim=0).values.double().cpu().numpy()
+            row = {"amp": amp, "domain": kind, "K": ctx.K, "steps": nsteps, "dt": dt, "t_end": t,
+                   "seconds": secs, "ms_per_step": 1e3 * secs / nsteps,
+                   "peak_p_prime": dict(zip(names, peak[kind].tolist())),
+                   "db_at_hz": {nm: dict(zip(map(str, octaves), db[kind][i, bins].round(2).tolist()))
+                                for i, nm in enumerate(names)}}
+            print(json.dumps(row), flush=True)
+            summary["runs"].append(row)
+            dg.dg_destroy(ctx)
+            del q, res
+            torch.cuda.empty_cache()
+        ref = db["box"]
+        for kind in db:
+            if kind == "box":
+                continue
+            diffs = {}
+            for i, nm in enumerate(names):
+                band = (ref[i] > ref[i].max() - 60) & (freqs > 20) & (freqs < 4000)
+                diffs[nm] = float(np.mean(np.abs(db[kind][i, band] - ref[i, band]))) if band.any() else None
+            summary.setdefault("mean_abs_db_vs_box", {}).setdefault(str(amp), {})[kind] = diffs
+        # reflection indicator of the far wall: sensor 3 (1 cm) against sensor 2 (2 cm)
+        for kind in db:
+            band = (db[kind][1] > db[kind][1].max() - 60) & (freqs > 300) & (freqs < 4000)
+            summary.setdefault("sensor3_minus_sensor2_db", {}).setdefault(str(amp), {})[kind] = \
+                float(np.mean(db[kind][2, band] - db[kind][1, band])) if band.any() else None
+    print(json.dumps({k: v for k, v in summary.items() if k != "runs"}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
