@@ -9,8 +9,9 @@ bell and near the outer boundary (Table 2 gives each sensor's distance from
 the bell and from the boundary): matching spectra mean the boundary
 treatment let the pulse out without disturbing the solution.  Here the
 domains are the synthetic trumpet domains of this package (box, sphere of
-radius 1.5, half domain), the sensors stand-ins placed by the same relations
-to the bell plane (x = 1) and to this box's walls (x = 1.8, y = 1), and every
+radius 1.5, half domain), the sensors stand-ins placed by their relation to
+the bell plane (x = 1): three at the same place in every domain, and on the
+axis a pair 2 cm and 1 cm before each domain's own far wall, and every
 signal is recorded every step by the library's probe kernel inside the
 captured step graph, with one fixed time step shared by all domains so that
 the spectra share their frequency bins.
@@ -36,19 +37,44 @@ GAMMA, RHO0, P0 = 1.4, 1.0, 1.0 / 1.4
 ALPHA = 2 * np.pi * 565.0 / 343.0
 HZ = 343.0            # one time unit is 1/343 s (lengths in metres, c0 = 1)
 P_REF = 2e-5 / 101325.0 * P0
+# sensors at the same place in every domain ...
 SENSORS = {
-    "sensor 1 (1 cm before the bell edge, 1 cm below the top wall)": (1.01, 0.99, 0.003),
-    "sensor 2 (on axis, 2 cm before the far wall)": (1.78, 0.0, 0.003),
-    "sensor 3 (on axis, 1 cm before the far wall)": (1.79, 0.0, 0.003),
+    "sensor 1 (1 cm before the bell edge, y = 0.99)": (1.01, 0.99, 0.003),
     "sensor 4 (in front of the bell, 0.57 up)": (1.29, 0.57, 0.003),
     "bore (1 cm inside the mouthpiece)": (0.01, 0.0, 0.003),
 }
+# ... and, per domain, on the axis 2 cm and 1 cm before its own far wall
+FAR = ("sensor 2 (on axis, 2 cm before the far wall)", "sensor 3 (on axis, 1 cm before the far wall)")
 DOMAINS = (("box", 50_000), ("sphere", 80_000), ("half", 30_000))
 
 
 def _torch():
     import torch
     return torch
+
+
+def far_wall(m, y=0.0, z=0.003):
+    """Largest x where the line (x, y, z) crosses a characteristic-outflow
+    face: the domain's outer boundary in front of the bell."""
+    from workloads import BC_OUTFLOW_CHAR
+    fv = np.array([(0, 1, 2), (0, 1, 3), (1, 2, 3), (0, 2, 3)])
+    k, f = np.nonzero(m["bc"] == BC_OUTFLOW_CHAR)
+    tri = m["xyz"][k[:, None], fv[f]]                       # [nf, 3 vertices, 3]
+    a, b, c = tri[:, 0], tri[:, 1], tri[:, 2]
+    # barycentric coordinates of (y, z) in the face's yz projection
+    d = (b[:, 1] - a[:, 1]) * (c[:, 2] - a[:, 2]) - (c[:, 1] - a[:, 1]) * (b[:, 2] - a[:, 2])
+    ok = np.abs(d) > 1e-14
+    d = np.where(ok, d, 1.0)
+    l1 = ((y - a[:, 1]) * (c[:, 2] - a[:, 2]) - (c[:, 1] - a[:, 1]) * (z - a[:, 2])) / d
+    l2 = ((b[:, 1] - a[:, 1]) * (z - a[:, 2]) - (y - a[:, 1]) * (b[:, 2] - a[:, 2])) / d
+    hit = ok & (l1 >= 0) & (l2 >= 0) & (l1 + l2 <= 1)
+    x = a[:, 0] + l1 * (b[:, 0] - a[:, 0]) + l2 * (c[:, 0] - a[:, 0])
+    return float(x[hit].max())
+
+
+def sensor_points(m):
+    xf = far_wall(m)
+    return list(SENSORS.values()) + [(xf - 0.02, 0.0, 0.003), (xf - 0.01, 0.0, 0.003)]
 
 
 def setup(kind, target_K, amp, N=4):
@@ -60,14 +86,15 @@ def setup(kind, target_K, amp, N=4):
     q = torch.zeros((ctx.K, 5, ctx.Np), dtype=torch.float32, device="cuda")
     res = torch.zeros_like(q)
     dg.dg_autotune(ctx, q, res)
-    dg.dg_probe_setup(ctx, list(SENSORS.values()))
-    return ctx, q, res
+    pts = sensor_points(m)
+    dg.dg_probe_setup(ctx, pts)
+    return ctx, q, res, pts
 
 
 def record(ctx, q, res, nsteps, dt, chunk=5000, label=""):
     """The sensors' p' after every step: device [nsteps, n_sensors]."""
     torch = _torch()
-    series = torch.empty((nsteps, len(SENSORS)), dtype=torch.float32, device="cuda")
+    series = torch.empty((nsteps, len(SENSORS) + len(FAR)), dtype=torch.float32, device="cuda")
     t, done, t0 = 0.0, 0, time.perf_counter()
     while done < nsteps:
         n = min(chunk, nsteps - done)
@@ -93,21 +120,22 @@ def main():
     ap.add_argument("--N", type=int, default=4)
     args = ap.parse_args()
     torch = _torch()
-    names = list(SENSORS)
+    names = list(SENSORS) + list(FAR)
     summary = {"sensors": SENSORS, "runs": []}
     for amp in [float(a) for a in args.amps.split(",") if a]:
         ctxs = {kind: setup(kind, K, amp, args.N) for kind, K in DOMAINS}
-        dt = 0.9 * min(dg.dg_stable_dt(c, q, 0.5) for c, q, _ in ctxs.values())
+        dt = 0.9 * min(dg.dg_stable_dt(c, q, 0.5) for c, q, _, _ in ctxs.values())
         nsteps = int(math.ceil(args.t_end / dt))
         freqs = np.arange(nsteps // 2 + 1) / (nsteps * dt) * HZ
-        octaves = [f for f in (62.5, 125, 250, 500, 1000, 2000, 4000, 8000) if f < freqs[-1]]
+        octaves = [f for f in (125, 250, 500, 1000, 2000, 4000, 8000) if f < freqs[-1]]
         bins = [int(np.argmin(np.abs(freqs - f))) for f in octaves]
         db, peak = {}, {}
-        for kind, (ctx, q, res) in ctxs.items():
+        for kind, (ctx, q, res, pts) in ctxs.items():
             s, t, secs = record(ctx, q, res, nsteps, dt, label=f"{kind} {amp}")
             db[kind] = spectra(s)
             peak[kind] = s.abs().max(dim=0).values.double().cpu().numpy()
             row = {"amp": amp, "domain": kind, "K": ctx.K, "steps": nsteps, "dt": dt, "t_end": t,
+                   "sensor_xyz": dict(zip(names, [list(p) for p in pts])),
                    "seconds": secs, "ms_per_step": 1e3 * secs / nsteps,
                    "peak_p_prime": dict(zip(names, peak[kind].tolist())),
                    "db_at_hz": {nm: dict(zip(map(str, octaves), db[kind][i, bins].round(2).tolist()))
@@ -122,15 +150,16 @@ def main():
             if kind == "box":
                 continue
             diffs = {}
-            for i, nm in enumerate(names):
+            for i, nm in enumerate(list(SENSORS)):   # the sensors every domain shares
                 band = (ref[i] > ref[i].max() - 60) & (freqs > 20) & (freqs < 4000)
                 diffs[nm] = float(np.mean(np.abs(db[kind][i, band] - ref[i, band]))) if band.any() else None
             summary.setdefault("mean_abs_db_vs_box", {}).setdefault(str(amp), {})[kind] = diffs
         # reflection indicator of the far wall: sensor 3 (1 cm) against sensor 2 (2 cm)
+        i2, i3 = len(SENSORS), len(SENSORS) + 1
         for kind in db:
-            band = (db[kind][1] > db[kind][1].max() - 60) & (freqs > 300) & (freqs < 4000)
+            band = (db[kind][i2] > db[kind][i2].max() - 60) & (freqs > 300) & (freqs < 4000)
             summary.setdefault("sensor3_minus_sensor2_db", {}).setdefault(str(amp), {})[kind] = \
-                float(np.mean(db[kind][2, band] - db[kind][1, band])) if band.any() else None
+                float(np.mean(db[kind][i3, band] - db[kind][i2, band])) if band.any() else None
     print(json.dumps({k: v for k, v in summary.items() if k != "runs"}), flush=True)
 
 
