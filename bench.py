@@ -39,10 +39,17 @@ def stage_bytes(K, Np, reads_res=True):
 
 
 def kernel_source_hash():
+    """Hash of the stage kernel's sources and compile flags."""
+    import importlib.util
     h = hashlib.sha256()
-    for name in ("csrc/kernels.hip", "csrc/physics.hpp", "csrc/kernels.hpp", "build.py"):
+    for name in ("csrc/kernels.hip", "csrc/physics.hpp", "csrc/kernels.hpp"):
         with open(os.path.join(ROOT, "paper_1710_03887_amd", name), "rb") as f:
             h.update(f.read())
+    spec = importlib.util.spec_from_file_location(
+        "dg_build", os.path.join(ROOT, "paper_1710_03887_amd", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    h.update(" ".join(mod.FLAGS).encode())
     return h.hexdigest()[:16]
 
 

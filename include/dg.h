@@ -362,6 +362,20 @@ int64_t dg_learned_faces(const dg_ctx* ctx, int64_t* faces);
 int dg_sample_traces(dg_ctx* ctx, const float* q, const int64_t* faces, int64_t nf, double norm,
                      float* X, float* Y, void* stream);
 
+/* ---- absorbing layer ----------------------------------------------------
+ * A sponge zone next to the outer boundary as a third closure beside the
+ * characteristic and learned ghosts (the absorbing-layer treatments the
+ * introduction surveys): every node relaxes towards the ambient state,
+ *     dq'/dt = f(q') - sigma(x) q',
+ * at a rate sigma(x) >= 0 the caller chooses (zero outside the layer,
+ * ramping up towards the boundary).  sigma: device FP32 [K][Np] in the
+ * library's node order (see dg_nodes), borrowed: it must stay valid while the
+ * context uses it; NULL turns the layer off.  Applies to dg_rhs, dg_step,
+ * dg_stage and the runs of this context (not to batches: dg_batch_create
+ * rejects a context with a layer).  Errors: DG_ENODEV on a host-only
+ * context. */
+int dg_set_damping(dg_ctx* ctx, const float* sigma);
+
 /* ---- pressure probes and spectra -----------------------------------------
  * Section 3 samples the pressure of each run at sensor points inside and
  * around the instrument and compares the frequency content of those signals

@@ -167,8 +167,10 @@ def face_traces(mesh, q, t, phys, learned=None):
     return qm, qp, nrm
 
 
-def rhs(mesh, q, t, phys, learned=None, pointwise_lambda=False):
-    """f(q) of Eq. 12 for the whole mesh: returns dq/dt [K, 5, Np]."""
+def rhs(mesh, q, t, phys, learned=None, pointwise_lambda=False, sigma=None):
+    """f(q) of Eq. 12 for the whole mesh: returns dq/dt [K, 5, Np].  With
+    sigma [K, Np] (an absorbing layer, this build's addition), every node
+    also relaxes towards the ambient state: - sigma (q - q0)."""
     ref = mesh.ref
     g = phys.gamma
     qn = np.transpose(q, (0, 2, 1))                       # [K, Np, 5]
@@ -188,8 +190,10 @@ def rhs(mesh, q, t, phys, learned=None, pointwise_lambda=False):
     dF = 0.5 * ((fm - fp) - lam[..., None] * (qm - qp))   # [K, 4, Nfp, 5]
     dF = dF * mesh.Fscale[:, :, None, None]
     lifted = ref.LIFT @ dF.reshape(mesh.K, 4 * ref.Nfp, 5)
-    out = -div + lifted
-    return np.transpose(out, (0, 2, 1)).copy()            # [K, 5, Np]
+    out = np.transpose(-div + lifted, (0, 2, 1)).copy()   # [K, 5, Np]
+    if sigma is not None:
+        out -= sigma[:, None, :] * (q - phys.q0[None, :, None])
+    return out
 
 
 def initial_state(prim, gamma):

@@ -53,13 +53,14 @@ def stable_dt(mesh, q, phys, cfl):
     return cfl / rate.max()
 
 
-def run(mesh, q, phys, nsteps, cfl=None, dts=None, t0=0.0, rhs_fn=None, learned=None):
+def run(mesh, q, phys, nsteps, cfl=None, dts=None, t0=0.0, rhs_fn=None, learned=None,
+        sigma=None):
     """Advance nsteps.  dt per step from `dts` if given, else from the CFL
     rule at the start of the step.  Returns (q, t, list of dt)."""
     from .euler import rhs as euler_rhs
     if rhs_fn is None:
         def rhs_fn(qq, tt):
-            return euler_rhs(mesh, qq, tt, phys, learned)
+            return euler_rhs(mesh, qq, tt, phys, learned, sigma=sigma)
     t = t0
     used = []
     res = None

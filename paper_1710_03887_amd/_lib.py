@@ -86,6 +86,7 @@ _SIGS = {
     "dg_set_learned_bc": (ctypes.c_int, [_vp, _vp, _f64, _f64, _f64, _f64]),
     "dg_learned_faces": (_i64, [_vp, _vp]),
     "dg_sample_traces": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, _vp, _vp, _vp]),
+    "dg_set_damping": (ctypes.c_int, [_vp, _vp]),
     "dg_probe_setup": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
     "dg_probe_sample": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "dg_run_probes": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, ctypes.POINTER(_f64), _vp, _vp]),
@@ -420,6 +421,16 @@ def dg_run_fixed(ctx, q, res, nsteps, dt, t=0.0, stream=None):
     _check(_lib.dg_run_fixed(ctx.handle, _ptr(q), _ptr(res), int(nsteps), float(dt),
                              ctypes.byref(tt), _stream(stream)), ctx.handle)
     return tt.value
+
+
+# ---- absorbing layer --------------------------------------------------------------------
+def dg_set_damping(ctx, sigma):
+    """Damping rate per node (device float32 [K, Np]) or None to turn the
+    layer off; the tensor must stay alive while the context uses it."""
+    if sigma is not None:
+        _check_device_f32(sigma, (ctx.K, ctx.Np), "sigma")
+    _check(_lib.dg_set_damping(ctx.handle, _ptr(sigma)), ctx.handle)
+    ctx.sigma = sigma   # keeps the tensor alive with the context
 
 
 # ---- pressure probes and spectra -----------------------------------------------------

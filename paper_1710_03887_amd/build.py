@@ -24,15 +24,18 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # FP32 division and square root from the hardware reciprocal and
+         # square-root instructions (1 ulp) instead of correctly rounded
+         # multi-instruction expansions
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+         "-Wall", "-Wno-unused-function"]
+
+
 def build(verbose=False):
     objs = []
-    flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             # FP32 division and square root from the hardware reciprocal and
-             # square-root instructions (1 ulp) instead of correctly rounded
-             # multi-instruction expansions
-             "-fno-hip-fp32-correctly-rounded-divide-sqrt",
-             "-Wall", "-Wno-unused-function"]
+    flags = FLAGS
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(HERE, "_build", src + ".o")

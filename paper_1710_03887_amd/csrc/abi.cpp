@@ -477,6 +477,14 @@ int dg_set_kernel(dg_ctx* c, int variant) {
 
 int dg_get_kernel(const dg_ctx* c) { return c ? c->dm.variant : -1; }
 
+int dg_set_damping(dg_ctx* c, const float* sigma) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  c->dm.sigma = sigma;
+  drop_graphs(c);
+  return DG_OK;
+}
+
 int dg_probe_setup(dg_ctx* c, const double* xyz, int32_t n, int64_t* elements_out,
                    double* weights_out) {
   if (!c) return fail(nullptr, DG_EINVAL, "null context");

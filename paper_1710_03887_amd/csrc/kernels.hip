@@ -449,6 +449,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     }
 
     // D. fixed-order reduction of the four partial sums, then the epilogue
+    // (absorbing-layer rates of this thread's outputs, loaded once for all
+    // five variables)
+    float sig[kOut];
+#pragma unroll
+    for (int i = 0; i < kOut; ++i) {
+      const int o = min(tid_t + i * kThreads, kTileE * MP - 1);
+      const int eo = o / MP, node = o - eo * MP;
+      sig[i] = (m.sigma && eo < ne && node < Np) ? m.sigma[(k0 + eo) * Np + node] : 0.0f;
+    }
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       __syncthreads();  // sP free (traces consumed / previous round read)
@@ -472,6 +481,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         for (int ww = 0; ww < kWaves; ++ww) acc_s += sP[(ww * kTileE + eo) * S::MPS + node];
         sum[i] = acc_s;
         qv[i] = sQ[eo * ST + v * Np + nd];
+        // absorbing layer: relaxation of q' towards zero at the node's rate
+        if (m.sigma) sum[i] -= sig[i] * qv[i];
         rv[i] = (MODE == MODE_STAGE && a_rk != 0.0f) ? sR[eo * ST + v * Np + nd] : 0.0f;
         gidx[i] = (k0 + eo) * ST + v * Np + nd;
       }

@@ -28,6 +28,8 @@ struct DeviceMesh {
   // learned ghost traces [n_learned][5][Np] (nodes 0..Nfp-1), or null; a
   // learned face's nbr entry is -(BC_LEARNED + 8 * its index)
   const float* lghost = nullptr;
+  // absorbing layer: damping rate per node [K][Np] (rhs -= sigma q'), or null
+  const float* sigma = nullptr;
   int variant = 0;                  // stage kernel: 0 tile-cooperative, 1 wavefront-private
   Phys phys;
 };

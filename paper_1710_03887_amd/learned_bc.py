@@ -167,25 +167,52 @@ def reflection_error(scene, amp, t_end, dt, nets=(), every=100, window=None, ble
         for i in range(len(runs)):
             d = states[i + 1][3][:, 4, :] - pb
             num[i] += float((Js[:, None] * d * d).sum())
+        if done % (20 * every) == 0 or done == nsteps:
+            print(f"reflection error: step {done}/{nsteps}", flush=True)
     errs = [math.sqrt(x / den) for x in num]
     return errs, [s / nsteps for s in secs]
 
 
-def char_domains(scene, amp, t_end, dt, scales, every=100):
-    """Interior error of the characteristic ghost on outer boxes `scales`
-    times the small box (each containing the small mesh element for
-    element), judged like reflection_error against the scene's larger
-    domain on the small box's elements.  Returns ([error per scale],
-    [seconds per step per scale], [elements per scale])."""
+def layer_sigma(ctx, scale, sigma_max, half=(1.15, 1.0, 1.0), center=(0.65, 0.0, 0.0)):
+    """Damping rates [K, Np] (device, library node order) of an absorbing
+    layer filling the shell between the small box (half extents `half` about
+    `center`) and the outer box `scale` times larger: sigma_max xi^2, xi the
+    node's largest normalized depth into the shell over the three axes."""
+    torch = _torch()
+    x = dg.dg_nodes(ctx)                                      # [K, Np, 3]
+    h = np.asarray(half)
+    depth = (np.abs(x - np.asarray(center)) - h) / ((scale - 1.0) * h)
+    xi = np.clip(depth, 0.0, 1.0).max(axis=-1)
+    return torch.tensor(sigma_max * xi * xi, dtype=torch.float32, device="cuda").contiguous()
+
+
+def outer_domains(scene, amp, t_end, dt, configs, every=100):
+    """Interior error on outer boxes `scale` times the small box (each
+    containing the small mesh element for element), closed by the
+    characteristic ghost, with an absorbing layer of peak rate sigma_max in
+    the shell around the small box when sigma_max > 0; judged like
+    reflection_error against the scene's larger domain on the small box's
+    elements.  configs: [(scale, sigma_max)].  Returns ([error], [seconds per
+    step], [elements]) per config."""
     torch = _torch()
     from workloads.trumpet import trumpet_nested
     big = scene.context("big", amp)
-    runs, maps = [], []
-    for sc in scales:
-        mid, small, emap = trumpet_nested(scene.target_K, sc)
-        assert np.array_equal(small["EToV"], scene.small["EToV"])
-        runs.append(dg.dg_mesh_setup(mid["xyz"], mid["EToV"], mid["bc"], 4, gamma=GAMMA, rho0=RHO0,
-                                     p0=P0, inflow_amp=amp, inflow_alpha=ALPHA))
+    runs, maps, keep = [], [], []
+    for sc, smax in configs:
+        if sc == 1.0:   # the small box itself (a layer then lies inside it: not judged fairly)
+            if smax > 0:
+                raise ValueError("an absorbing layer needs an outer box larger than the small box")
+            mid, emap = scene.small, np.arange(len(scene.small["EToV"]))
+        else:
+            mid, small, emap = trumpet_nested(scene.target_K, sc)
+            assert np.array_equal(small["EToV"], scene.small["EToV"])
+        c = dg.dg_mesh_setup(mid["xyz"], mid["EToV"], mid["bc"], 4, gamma=GAMMA, rho0=RHO0,
+                             p0=P0, inflow_amp=amp, inflow_alpha=ALPHA)
+        if smax > 0:
+            sig = layer_sigma(c, sc, smax)
+            dg.dg_set_damping(c, sig)
+            keep.append(sig)
+        runs.append(c)
         maps.append(torch.tensor(emap, dtype=torch.int64, device="cuda"))
     emap_big = torch.tensor(scene.emap, dtype=torch.int64, device="cuda")
     Js = _weights(big)[emap_big]
@@ -211,8 +238,15 @@ def char_domains(scene, amp, t_end, dt, scales, every=100):
         for i in range(len(runs)):
             d = states[i + 1][3][:, 4, :][maps[i]] - pb
             num[i] += float((Js[:, None] * d * d).sum())
+        if done % (20 * every) == 0 or done == nsteps:
+            print(f"outer domains: step {done}/{nsteps}", flush=True)
     return ([math.sqrt(x / den) for x in num], [s_ / nsteps for s_ in secs],
             [c.K for c in runs])
+
+
+def char_domains(scene, amp, t_end, dt, scales, every=100):
+    """outer_domains with the characteristic ghost alone on each box."""
+    return outer_domains(scene, amp, t_end, dt, [(sc, 0.0) for sc in scales], every)
 
 
 def choose_blend(scene, net, window, amp, t_end, dt, blends=(0.25, 0.5, 0.75, 1.0)):
@@ -244,10 +278,26 @@ def main():
     ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--char-scales", default="1.25,1.5,2.0",
                     help="outer boxes (x the small box) run with the characteristic ghost")
+    ap.add_argument("--layers", default="",
+                    help="absorbing-layer runs scale:sigma_max,... (shell between the small box "
+                         "and the outer box)")
+    ap.add_argument("--domains-only", action="store_true",
+                    help="skip the learned closure: only the outer-box and layer runs at the "
+                         "last evaluation amplitude")
     args = ap.parse_args()
     torch = _torch()
     t0 = time.perf_counter()
     scene = Scene(args.target)
+    if args.domains_only:
+        a = float(args.eval_amps.split(",")[-1])
+        dt = stable_dt(scene.context("big", a * P0))
+        configs = [(1.0, 0.0)] + [(float(x), 0.0) for x in args.char_scales.split(",") if x]
+        configs += [tuple(float(v) for v in x.split(":")) for x in args.layers.split(",") if x]
+        errs, secs, Ks = outer_domains(scene, a * P0, args.t_end, dt, configs)
+        rows = [{"scale": sc, "sigma_max": sm, "K": K, "err": e, "s_per_step": t_}
+                for (sc, sm), e, t_, K in zip(configs, errs, secs, Ks)]
+        print(json.dumps({"amp": a, "dt": dt, "domains": rows}), flush=True)
+        return
     Xs, Ys, Ls, dt = [], [], [], None
     for a in [float(x) for x in args.train_amps.split(",")]:
         X, Y, L, dt = sample_run(scene, a * P0, args.t_end, dt=dt)

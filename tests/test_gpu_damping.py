@@ -1,0 +1,87 @@
+"""The absorbing layer (dg_set_damping) against the FP64 oracle's
+rhs - sigma (q - q0), with the bars of the plain operator (2e-5 relative L2
+for one FP32 right-hand side, 2e-3 split-BF16, 1e-5 for p' after 100
+steps), for both stage-kernel variants."""
+import numpy as np
+import pytest
+
+import paper_1710_03887_amd as dg
+from oracle import euler, timestep, norms
+from workloads import (box_kuhn, gaussian_pulse, BC_OUTFLOW_CHAR, BC_WALL, BC_INFLOW,
+                       BC_PASSTHRU)
+from helpers import Pair, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _sigma(pair, smax=4.0):
+    """A layer along x+ : zero for x < 0.2, then s_max ((x - 0.2)/0.8)^2."""
+    x = pair.mesh.x[..., 0]
+    return smax * np.clip((x - 0.2) / 0.8, 0.0, None) ** 2         # oracle node order
+
+
+def _to_lib_nodes(pair, a):
+    return torch.tensor(a[:, pair.perm], dtype=torch.float32, device="cuda").contiguous()
+
+
+@pytest.mark.parametrize("N,variant,precision", [(3, 0, dg.DG_FP32), (4, 0, dg.DG_FP32),
+                                                 (4, 1, dg.DG_FP32), (4, 0, dg.DG_SPLIT_BF16)])
+def test_rhs_parity_with_layer(N, variant, precision):
+    phys = euler.Physics(u0=(0.03, 0.0, -0.02), amp=0.05 / 1.4, alpha=10.35)
+    bc = {"x-": BC_INFLOW, "x+": BC_OUTFLOW_CHAR, "y-": BC_WALL, "y+": BC_PASSTHRU,
+          "z-": BC_OUTFLOW_CHAR, "z+": BC_OUTFLOW_CHAR}
+    pair = Pair(box_kuhn((4, 3, 3), jitter=0.05, seed=12, bc=bc), N, phys, precision=precision)
+    if variant:
+        dg.dg_set_kernel(pair.ctx, variant)
+    prim = gaussian_pulse(pair.mesh.x, 0.05 * phys.p0, 0.5, (0.5, 0.0, 0.1), phys.rho0, phys.p0,
+                          phys.gamma)
+    q = euler.initial_state(prim, phys.gamma)
+    sig = _sigma(pair)
+    sd = _to_lib_nodes(pair, sig)
+    dg.dg_set_damping(pair.ctx, sd)
+    qd = pair.to_device(q)
+    rd = torch.full_like(qd, float("nan"))
+    dg.dg_rhs(pair.ctx, qd, rd, 0.13)
+    torch.cuda.synchronize()
+    r_or = euler.rhs(pair.mesh, q, 0.13, phys, sigma=sig)
+    err = rel_l2(pair.mesh, pair.rates_from_device(rd), r_or)
+    tol = 2e-3 if precision == dg.DG_SPLIT_BF16 else 2e-5
+    print(f"N={N} variant {variant} precision {precision}: rhs with layer rel L2 {err:.3e}")
+    assert err < tol
+    # the layer's term is really there (the plain operator differs by far more than the bar
+    # of the FP32 form)
+    assert rel_l2(pair.mesh, pair.rates_from_device(rd), euler.rhs(pair.mesh, q, 0.13, phys)) > 1e-2
+    dg.dg_set_damping(pair.ctx, None)
+    dg.dg_rhs(pair.ctx, qd, rd, 0.13)
+    torch.cuda.synchronize()
+    assert rel_l2(pair.mesh, pair.rates_from_device(rd), euler.rhs(pair.mesh, q, 0.13, phys)) < tol
+
+
+def test_run_parity_with_layer_100_steps():
+    phys = euler.Physics()
+    pair = Pair(box_kuhn(5, jitter=0.05, seed=2), 2, phys)
+    prim = gaussian_pulse(pair.mesh.x, 0.1 * phys.p0, 0.2, (0.3, 0.0, 0.0), phys.rho0, phys.p0,
+                          phys.gamma)
+    q0 = euler.initial_state(prim, phys.gamma)
+    sig = _sigma(pair, 8.0)
+    dg.dg_set_damping(pair.ctx, _to_lib_nodes(pair, sig))
+    q_or, t_or, dts = timestep.run(pair.mesh, q0, phys, 100, cfl=0.5, sigma=sig)
+    qd = pair.to_device(q0)
+    res = torch.zeros_like(qd)
+    t, _ = dg.dg_run(pair.ctx, qd, res, 100, 0.5, 0.0)
+    assert abs(t / t_or - 1) < 1e-6
+    err = norms.rel_l2_pressure(pair.mesh, pair.from_device(qd), q_or, phys)
+    q_plain, _, _ = timestep.run(pair.mesh, q0, phys, 100, dts=dts)
+    gap = norms.rel_l2_pressure(pair.mesh, q_plain, q_or, phys)
+    print(f"100 steps with layer: p' rel L2 {err:.3e} (layer changes p' by {gap:.2e})")
+    assert err < 1e-5 and gap > 1e-2
+
+
+def test_batch_rejects_layer():
+    phys = euler.Physics()
+    pair = Pair(box_kuhn(2), 2, phys)
+    dg.dg_set_damping(pair.ctx, torch.zeros((pair.ctx.K, pair.ctx.Np), device="cuda"))
+    with pytest.raises(dg.DGError):
+        dg.dg_batch_create([pair.ctx], 4)
