@@ -372,8 +372,9 @@ int dg_sample_traces(dg_ctx* ctx, const float* q, const int64_t* faces, int64_t 
  * library's node order (see dg_nodes), borrowed: it must stay valid while the
  * context uses it; NULL turns the layer off.  Applies to dg_rhs, dg_step,
  * dg_stage and the runs of this context (not to batches: dg_batch_create
- * rejects a context with a layer).  Errors: DG_ENODEV on a host-only
- * context. */
+ * rejects a context with a layer).  While a layer is set the
+ * tile-cooperative stage kernel runs whatever dg_set_kernel chose.  Errors:
+ * DG_ENODEV on a host-only context. */
 int dg_set_damping(dg_ctx* ctx, const float* sigma);
 
 /* ---- pressure probes and spectra -----------------------------------------

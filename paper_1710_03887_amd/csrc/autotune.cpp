@@ -101,7 +101,7 @@ int dg_autotune(dg_ctx* c, const float* q, float* res, const char* cache_path, i
   hipStream_t s = static_cast<hipStream_t>(stream);
   const std::string key = "single/N" + std::to_string(c->dm.N) + "/K" + std::to_string(c->dm.K) +
                           "/prec" + std::to_string(c->dm.precision) + "/" + device_key();
-  const bool wave_ok = dg::wave_stage_supported(c->dm.N, c->dm.precision);
+  const bool wave_ok = dg::wave_stage_supported(c->dm.N, c->dm.precision) && !c->dm.sigma;
   int best = 0, best_v = 0;
   if (!cache_lookup(cache_path, key, &best, &best_v) || best < 1 ||
       best > c->max_blocks_per_cu || best_v < 0 || best_v > 1 || (best_v == 1 && !wave_ok)) {

@@ -113,7 +113,7 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-template <int N, int MODE, bool MOVING, int PREC>
+template <int N, int MODE, bool MOVING, int PREC, bool DAMP>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel(DeviceMesh m, const float* __restrict__ q_in,
                                                          float* __restrict__ q_out,
                                                          float* __restrict__ res,
@@ -449,14 +449,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     }
 
     // D. fixed-order reduction of the four partial sums, then the epilogue
-    // (absorbing-layer rates of this thread's outputs, loaded once for all
-    // five variables)
-    float sig[kOut];
+    // (with an absorbing layer, the rates of this thread's outputs, loaded
+    // once for all five variables)
+    float sig[DAMP ? kOut : 1];
+    if (DAMP) {
 #pragma unroll
-    for (int i = 0; i < kOut; ++i) {
-      const int o = min(tid_t + i * kThreads, kTileE * MP - 1);
-      const int eo = o / MP, node = o - eo * MP;
-      sig[i] = (m.sigma && eo < ne && node < Np) ? m.sigma[(k0 + eo) * Np + node] : 0.0f;
+      for (int i = 0; i < kOut; ++i) {
+        const int o = min(tid_t + i * kThreads, kTileE * MP - 1);
+        const int eo = o / MP, node = o - eo * MP;
+        sig[i] = (eo < ne && node < Np) ? m.sigma[(k0 + eo) * Np + node] : 0.0f;
+      }
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -482,7 +484,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         sum[i] = acc_s;
         qv[i] = sQ[eo * ST + v * Np + nd];
         // absorbing layer: relaxation of q' towards zero at the node's rate
-        if (m.sigma) sum[i] -= sig[i] * qv[i];
+        if (DAMP) sum[i] -= sig[DAMP ? i : 0] * qv[i];
         rv[i] = (MODE == MODE_STAGE && a_rk != 0.0f) ? sR[eo * ST + v * Np + nd] : 0.0f;
         gidx[i] = (k0 + eo) * ST + v * Np + nd;
       }
@@ -647,8 +649,13 @@ __global__ void prim_kernel(DeviceMesh m, const float* __restrict__ in, float* _
 template <int N, int MODE, bool MOVING, int PREC>
 hipError_t set_lds_limit() {
   const int lds = int(Shape<N, PREC>::total * sizeof(float));
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<N, MODE, MOVING, PREC>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipError_t e = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&stage_kernel<N, MODE, MOVING, PREC, false>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<N, MODE, MOVING, PREC, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  return e;
 }
 
 template <int N, int PREC>
@@ -660,7 +667,7 @@ hipError_t stage_prepare_prec(int* blocks_per_cu) {
   if (e != hipSuccess) return e;
   int nb = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &nb, reinterpret_cast<const void*>(&stage_kernel<N, MODE_STAGE, true, PREC>), kThreads,
+      &nb, reinterpret_cast<const void*>(&stage_kernel<N, MODE_STAGE, true, PREC, false>), kThreads,
       Shape<N, PREC>::total * sizeof(float));
   if (e != hipSuccess) return e;
   *blocks_per_cu = std::max(nb, 1);
@@ -678,9 +685,12 @@ void stage_launch(int blocks, hipStream_t s, const DeviceMesh& m, const float* q
                   float* res, float* out, float a, float b, double c, double t_host,
                   double dt_host, RunScalars* run, int rate_out) {
   const size_t lds = size_t(Shape<N, PREC>::total) * sizeof(float);
-  stage_kernel<N, MODE, MOVING, PREC><<<blocks, kThreads, lds, s>>>(m, q_in, q_out, res, out, a, b,
-                                                                    c, t_host, dt_host, run,
-                                                                    rate_out);
+  if (m.sigma)
+    stage_kernel<N, MODE, MOVING, PREC, true><<<blocks, kThreads, lds, s>>>(
+        m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out);
+  else
+    stage_kernel<N, MODE, MOVING, PREC, false><<<blocks, kThreads, lds, s>>>(
+        m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out);
 }
 
 template <int N, int PREC>
@@ -827,7 +837,7 @@ hipError_t prepare_kernels(int N, int precision, int* blocks_per_cu) {
 hipError_t launch_stage(const DeviceMesh& m, int mode, const float* q_in, float* q_out, float* res,
                         float* out, float a, float b, double c, double t_host, double dt_host,
                         RunScalars* run, int rate_out, hipStream_t s) {
-  if (m.variant == 1 && wave_stage_supported(m.N, m.precision))
+  if (m.variant == 1 && wave_stage_supported(m.N, m.precision) && !m.sigma)
     return launch_wave_stage(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run,
                              rate_out, s);
   switch (m.N) {

@@ -368,9 +368,7 @@ void wave_stage_kernel(DeviceMesh m, const float* __restrict__ q_in, float* __re
       wave_sync();
       for (int idx = lane; idx < ne * Np; idx += 64) {
         const int el = idx / Np, node = idx - el * Np;
-        float a = sT[el * S::MP + node];
-        // absorbing layer: relaxation of q' towards zero at the node's rate
-        if (m.sigma) a -= m.sigma[(k0 + el) * Np + node] * sQ[el * ST + v * Np + node];
+        const float a = sT[el * S::MP + node];
         const int64_t gx = (k0 + el) * ST + v * Np + node;
         if (MODE == MODE_RHS) {
           out[gx] = a;

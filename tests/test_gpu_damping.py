@@ -1,7 +1,8 @@
 """The absorbing layer (dg_set_damping) against the FP64 oracle's
 rhs - sigma (q - q0), with the bars of the plain operator (2e-5 relative L2
 for one FP32 right-hand side, 2e-3 split-BF16, 1e-5 for p' after 100
-steps), for both stage-kernel variants."""
+steps).  A context set to the wavefront-private kernel runs the
+tile-cooperative one while a layer is set (checked through the same bars)."""
 import numpy as np
 import pytest
 
