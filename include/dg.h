@@ -64,6 +64,21 @@ extern "C" {
 /* ---- setup flags -------------------------------------------------------- */
 #define DG_SETUP_HOST_ONLY 1 /* build host data only (no GPU needed); device
                                 calls then return DG_ENODEV                  */
+#define DG_SETUP_QUADRATURE 2 /* the paper's own discretization (Appendix A):
+                                the weak form integrated with Gauss quadrature
+                                exact to degree 2N in the volume and 2N + 1
+                                on the faces (instead of the nodal strong form),
+                                advanced by a two-stage second-order
+                                Runge-Kutta scheme (SSP form) instead of
+                                LSERK4; N = 1 or 2, FP32 form.  Same state
+                                layout (nodal values of the order-N nodes, the
+                                same polynomial space).  dg_rhs, dg_step
+                                (one RK2 step; res unused), dg_run,
+                                dg_run_fixed, dg_run_probes and the probes
+                                apply; dg_stage, dg_set_kernel(1),
+                                dg_set_damping, the learned closure and
+                                batches do not (DG_EINVAL); dg_autotune
+                                returns at once with blocks_per_cu = 0.      */
 
 typedef struct dg_ctx dg_ctx;
 
@@ -84,7 +99,7 @@ typedef struct dg_ctx dg_ctx;
  * inflow_amp, inflow_alpha   pulse p0 + amp (1 - cos(alpha t))/2 for
  *          0 <= t < 2 pi/alpha on DG_BC_INFLOW faces (Section 2.4).
  * precision  DG_FP32 or DG_SPLIT_BF16.
- * flags    0 or DG_SETUP_HOST_ONLY.
+ * flags    0 or an OR of DG_SETUP_HOST_ONLY and DG_SETUP_QUADRATURE.
  */
 typedef struct dg_mesh_desc {
   int32_t N;

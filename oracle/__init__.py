@@ -24,3 +24,4 @@ different route from the orthonormal-basis construction used by the library.
 Functions without an independent pin say "parity unpinned" in their docstring.
 """
 from . import nodes, operators, mesh, euler, timestep, norms  # noqa: F401
+# (probes, mlp and quadrature are imported by name where used)

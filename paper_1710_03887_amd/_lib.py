@@ -17,6 +17,7 @@ DG_OK, DG_EINVAL, DG_EMESH, DG_ENOMEM, DG_EHIP, DG_ENONPHYS, DG_ENODEV = 0, -1, 
 DG_BC_INTERIOR, DG_BC_OUTFLOW_CHAR, DG_BC_PASSTHRU, DG_BC_WALL, DG_BC_INFLOW, DG_BC_LEARNED = range(6)
 DG_FP32, DG_SPLIT_BF16 = 0, 1
 DG_SETUP_HOST_ONLY = 1
+DG_SETUP_QUADRATURE = 2
 
 _ERRNAMES = {DG_EINVAL: "DG_EINVAL", DG_EMESH: "DG_EMESH", DG_ENOMEM: "DG_ENOMEM",
              DG_EHIP: "DG_EHIP", DG_ENONPHYS: "DG_ENONPHYS", DG_ENODEV: "DG_ENODEV"}
@@ -175,7 +176,9 @@ class Context:
 
 def dg_mesh_setup(xyz, EToV, bc, N, gamma=1.4, rho0=1.0, u0=(0.0, 0.0, 0.0), p0=1.0 / 1.4,
                   precision=DG_FP32, inflow_amp=0.0, inflow_alpha=2 * np.pi * 565.0 / 343.0,
-                  host_only=False, stream=None):
+                  host_only=False, quadrature=False, stream=None):
+    """Set up a mesh; quadrature=True selects the weak form with Gauss
+    quadrature and RK2 (DG_SETUP_QUADRATURE) instead of the nodal scheme."""
     xyz = np.ascontiguousarray(xyz, dtype=np.float64)
     EToV = np.ascontiguousarray(EToV, dtype=np.int64)
     bc = np.ascontiguousarray(bc, dtype=np.int8)
@@ -185,7 +188,8 @@ def dg_mesh_setup(xyz, EToV, bc, N, gamma=1.4, rho0=1.0, u0=(0.0, 0.0, 0.0), p0=
     d = dg_mesh_desc(N=N, precision=precision, K=K, xyz=xyz.ctypes.data, EToV=EToV.ctypes.data,
                      bc=bc.ctypes.data, gamma=gamma, rho0=rho0, u0=(_f64 * 3)(*u0), p0=p0,
                      inflow_amp=inflow_amp, inflow_alpha=inflow_alpha,
-                     flags=DG_SETUP_HOST_ONLY if host_only else 0, reserved=0)
+                     flags=(DG_SETUP_HOST_ONLY if host_only else 0) |
+                     (DG_SETUP_QUADRATURE if quadrature else 0), reserved=0)
     h = _vp()
     _check(_lib.dg_mesh_setup(ctypes.byref(d), None if host_only else _stream(stream),
                               ctypes.byref(h)), None)

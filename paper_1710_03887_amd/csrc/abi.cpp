@@ -140,6 +140,18 @@ int build_device(dg_ctx* c, hipStream_t s) {
     c->lbc.ghost = dGh;
     c->lbc.nl = nl;
   }
+  if (c->dm.scheme == 1) {
+    dg::QuadOps Q;
+    const std::string msg = dg::build_quadrature(ops, Q);
+    if (!msg.empty()) return fail(c, DG_EINVAL, msg);
+    std::vector<float> tab;
+    for (const auto* v : {&Q.Bv, &Q.Dw, &Q.Bf, &Q.Lq, &Q.Bnb})
+      for (double x : *v) tab.push_back(float(x));
+    if (tab.size() != dg::quad_table_floats(c->dm.N)) return fail(c, DG_EINVAL, "quadrature table size");
+    float* dT;
+    if ((rc = upload(c, tab.data(), tab.size(), &dT, s))) return rc;
+    c->dm.qtab = dT;
+  }
   if ((rc = upload<dg::RunScalars>(c, nullptr, 1, &c->run, s))) return rc;
   c->host_run = dg::RunScalars{};
   c->host_run.first_bad = -1;
@@ -189,6 +201,19 @@ hipError_t enqueue_stages(dg_ctx* c, float* q, float* res, bool start_in_q, doub
   return hipSuccess;
 }
 
+// One two-stage second-order Runge-Kutta step of the quadrature scheme
+// (strong-stability-preserving form): q1 = q + dt L(q, t);
+// q <- (q + q1 + dt L(q1, t + dt)) / 2.  The state ends in q.
+hipError_t enqueue_rk2(dg_ctx* c, float* q, double t, double dt, dg::RunScalars* run,
+                       hipStream_t s) {
+  hipError_t e = dg::launch_quad(c->dm, dg::MODE_STAGE, q, nullptr, c->qbuf, nullptr, 0.0f, 1.0f,
+                                 0.0, t, dt, run, 0, s);
+  if (e == hipSuccess)
+    e = dg::launch_quad(c->dm, dg::MODE_STAGE, c->qbuf, q, q, nullptr, 0.5f, 0.5f, 1.0, t, dt,
+                        run, 1, s);
+  return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -201,7 +226,11 @@ int dg_mesh_setup(const dg_mesh_desc* d, void* stream, dg_ctx** out) {
   if (d->K <= 0) return fail(nullptr, DG_EINVAL, "K must be positive");
   if (d->precision != DG_FP32 && d->precision != DG_SPLIT_BF16)
     return fail(nullptr, DG_EINVAL, "unknown precision");
-  if ((d->flags & ~DG_SETUP_HOST_ONLY) != 0) return fail(nullptr, DG_EINVAL, "unknown flags");
+  if ((d->flags & ~(DG_SETUP_HOST_ONLY | DG_SETUP_QUADRATURE)) != 0)
+    return fail(nullptr, DG_EINVAL, "unknown flags");
+  const bool quad = (d->flags & DG_SETUP_QUADRATURE) != 0;
+  if (quad && (d->N > 2 || d->precision != DG_FP32))
+    return fail(nullptr, DG_EINVAL, "the quadrature scheme needs N <= 2 and the FP32 form");
   if (!(d->gamma > 1.0) || !(d->rho0 > 0.0) || !(d->p0 > 0.0))
     return fail(nullptr, DG_EINVAL, "need gamma > 1, rho0 > 0, p0 > 0");
 
@@ -215,6 +244,7 @@ int dg_mesh_setup(const dg_mesh_desc* d, void* stream, dg_ctx** out) {
     return fail(nullptr, arg ? DG_EINVAL : DG_EMESH, msg);
   }
   c->host_only = (d->flags & DG_SETUP_HOST_ONLY) != 0;
+  c->dm.scheme = quad ? 1 : 0;
   c->dm.N = d->N;
   c->dm.Np = c->ops.Np;
   c->dm.Nfp = c->ops.Nfp;
@@ -304,8 +334,12 @@ int dg_rhs(dg_ctx* c, const float* q, float* rhs, double t, void* stream) {
   int rc = need_device(c);
   if (rc) return rc;
   if (!q || !rhs) return fail(c, DG_EINVAL, "null state pointer");
-  hipError_t e = stage(c, dg::MODE_RHS, q, nullptr, nullptr, rhs, 0.f, 0.f, 0.0, t,
-                                  0.0, nullptr, 0, static_cast<hipStream_t>(stream));
+  hipError_t e =
+      c->dm.scheme == 1
+          ? dg::launch_quad(c->dm, dg::MODE_RHS, q, nullptr, nullptr, rhs, 0.f, 0.f, 0.0, t, 0.0,
+                            nullptr, 0, static_cast<hipStream_t>(stream))
+          : stage(c, dg::MODE_RHS, q, nullptr, nullptr, rhs, 0.f, 0.f, 0.0, t, 0.0, nullptr, 0,
+                  static_cast<hipStream_t>(stream));
   return e == hipSuccess ? DG_OK : hip_fail(c, e, "stage launch");
 }
 
@@ -314,6 +348,10 @@ int dg_step(dg_ctx* c, float* q, float* res, double t, double dt, void* stream) 
   if (rc) return rc;
   if (!q || !res) return fail(c, DG_EINVAL, "null state pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->dm.scheme == 1) {
+    const hipError_t e = enqueue_rk2(c, q, t, dt, nullptr, s);
+    return e == hipSuccess ? DG_OK : hip_fail(c, e, "stage launch");
+  }
   hipError_t e = enqueue_stages(c, q, res, true, t, dt, nullptr, s);
   if (e != hipSuccess) return hip_fail(c, e, "stage launch");
   // five stages end in the context buffer
@@ -328,6 +366,7 @@ int dg_stage(dg_ctx* c, const float* q_in, float* q_out, float* res, double a, d
   if (rc) return rc;
   if (!q_in || !q_out || !res) return fail(c, DG_EINVAL, "null state pointer");
   if (q_in == q_out) return fail(c, DG_EINVAL, "q_in and q_out must differ");
+  if (c->dm.scheme == 1) return fail(c, DG_EINVAL, "no low-storage stage in the quadrature scheme");
   hipError_t e = stage(c, dg::MODE_STAGE, q_in, q_out, res, nullptr, float(a),
                                   float(b), 0.0, t_stage, dt, nullptr, 0,
                                   static_cast<hipStream_t>(stream));
@@ -386,6 +425,46 @@ int run_impl(dg_ctx* c, float* q, float* res, int64_t nsteps, double cfl, double
   // of the step before
   e = dg::launch_rate(c->dm, q, c->run, s);
   if (e != hipSuccess) return hip_fail(c, e, "rate launch");
+
+  if (c->dm.scheme == 1) {  // quadrature scheme: a graph of one RK2 step, state stays in q
+    if (nsteps >= 1 && (gc.q != q || !gc.exec)) {
+      if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+      gc = dg::GraphCache{};
+      hipStream_t cs = c->capture_stream;
+      e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+      hipError_t le = dg::launch_finalize(c->run, cs);
+      if (le == hipSuccess) le = enqueue_rk2(c, q, 0.0, 0.0, c->run, cs);
+      if (le == hipSuccess) le = dg::launch_advance(c->run, cs);
+      if (le == hipSuccess && series) le = dg::launch_probe(c->probe_dev, np, c->dm, q, nullptr, c->run, cs);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(cs, &g);
+      if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(c, le, "launch during capture");
+      }
+      if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+      gc.exec = ex;
+      gc.q = q;
+      gc.res = res;
+    }
+    for (int64_t k = 0; k < nsteps; ++k) {
+      e = hipGraphLaunch(gc.exec, s);
+      if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    }
+    e = hipMemcpyAsync(&c->host_run, c->run, sizeof(dg::RunScalars), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "dg_run sync");
+    *t_inout = c->host_run.t;
+    if (dt_last) *dt_last = c->host_run.dt;
+    c->last_bad = c->host_run.first_bad;
+    if (c->last_bad >= 0) return fail(c, DG_ENONPHYS, "non-physical state during dg_run");
+    return DG_OK;
+  }
 
   // a graph of two steps (ten stage swaps) leaves the state in q
   if (nsteps >= 2 && (gc.q != q || gc.res != res || !gc.exec)) {
@@ -468,7 +547,7 @@ int dg_set_kernel(dg_ctx* c, int variant) {
   int rc = need_device(c);
   if (rc) return rc;
   if (variant != 0 && variant != 1) return fail(c, DG_EINVAL, "variant must be 0 or 1");
-  if (variant == 1 && !dg::wave_stage_supported(c->dm.N, c->dm.precision))
+  if (variant == 1 && (c->dm.scheme == 1 || !dg::wave_stage_supported(c->dm.N, c->dm.precision)))
     return fail(c, DG_EINVAL, "the wavefront-private stage kernel needs the FP32 form and N <= 4");
   c->dm.variant = variant;
   drop_graphs(c);
@@ -480,6 +559,7 @@ int dg_get_kernel(const dg_ctx* c) { return c ? c->dm.variant : -1; }
 int dg_set_damping(dg_ctx* c, const float* sigma) {
   int rc = need_device(c);
   if (rc) return rc;
+  if (c->dm.scheme == 1 && sigma) return fail(c, DG_EINVAL, "no absorbing layer in the quadrature scheme");
   c->dm.sigma = sigma;
   drop_graphs(c);
   return DG_OK;

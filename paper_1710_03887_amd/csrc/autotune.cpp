@@ -99,6 +99,10 @@ int dg_autotune(dg_ctx* c, const float* q, float* res, const char* cache_path, i
     return DG_EINVAL;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->dm.scheme == 1) {  // the quadrature kernel has one launch shape
+    if (blocks_per_cu) *blocks_per_cu = 0;
+    return DG_OK;
+  }
   const std::string key = "single/N" + std::to_string(c->dm.N) + "/K" + std::to_string(c->dm.K) +
                           "/prec" + std::to_string(c->dm.precision) + "/" + device_key();
   const bool wave_ok = dg::wave_stage_supported(c->dm.N, c->dm.precision) && !c->dm.sigma;

@@ -12,6 +12,7 @@
 #include "kernels.hpp"
 #include "mlp.hpp"
 #include "probes.hpp"
+#include "quad.hpp"
 #include "setup.hpp"
 
 namespace dg {

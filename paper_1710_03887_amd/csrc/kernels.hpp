@@ -31,6 +31,9 @@ struct DeviceMesh {
   // absorbing layer: damping rate per node [K][Np] (rhs -= sigma q'), or null
   const float* sigma = nullptr;
   int variant = 0;                  // stage kernel: 0 tile-cooperative, 1 wavefront-private
+  // 0: nodal strong form + LSERK4; 1: weak form with Gauss quadrature + RK2
+  int scheme = 0;
+  const float* qtab = nullptr;      // quadrature-scheme tables (scheme 1)
   Phys phys;
 };
 

@@ -604,4 +604,168 @@ void interpolation_weights(const RefOps& ops, const double rst[3], double* w) {
   }
 }
 
+namespace {
+
+// Gauss-Jacobi rule with n points for the weight (1-x)^al on [-1,1]: the
+// zeros of P_n^(al,0) by Newton's method from the Chebyshev-Gauss points,
+// weights 1 / sum_{k<n} p_k(x)^2 (p_k the orthonormal Jacobi polynomials).
+void gauss_jacobi(int n, double al, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double z = -std::cos(M_PI * (2.0 * j + 1.0) / (2.0 * n));
+    for (int it = 0; it < 200; ++it) {
+      // deflate the zeros already found
+      double f = jacobi_norm(z, n, al, 0.0), df = jacobi_norm_deriv(z, n, al, 0.0);
+      double sum = 0.0;
+      for (int i = 0; i < j; ++i) sum += 1.0 / (z - x[i]);
+      const double dz = f / (df - f * sum);
+      z -= dz;
+      if (std::fabs(dz) < 1e-15) break;
+    }
+    x[j] = z;
+  }
+  std::sort(x.begin(), x.end());
+  for (int j = 0; j < n; ++j) {
+    double s2 = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double pk = jacobi_norm(x[j], k, al, 0.0);
+      s2 += pk * pk;
+    }
+    w[j] = 1.0 / s2;
+  }
+}
+
+// Lagrange basis of the nodes (values, and reference derivatives when d is
+// not null: d[a * Np + i]) at a reference point.
+void lagrange_at(const RefOps& ops, const double rst[3], double* l, double* d) {
+  const int N = ops.N, Np = ops.Np;
+  std::vector<double> psi(Np), dpsi(3 * size_t(Np));
+  int m = 0;
+  for (int i = 0; i <= N; ++i)
+    for (int j = 0; j <= N - i; ++j)
+      for (int k = 0; k <= N - i - j; ++k, ++m)
+        basis3(i, j, k, rst[0], rst[1], rst[2], psi[m], dpsi[m], dpsi[Np + m], dpsi[2 * Np + m]);
+  for (int i = 0; i < Np; ++i) {
+    double v = 0.0, dr = 0.0, ds = 0.0, dt = 0.0;
+    for (int mm = 0; mm < Np; ++mm) {
+      const double c = ops.Vinv[size_t(mm) * Np + i];
+      v += psi[mm] * c;
+      dr += dpsi[mm] * c;
+      ds += dpsi[Np + mm] * c;
+      dt += dpsi[2 * Np + mm] * c;
+    }
+    l[i] = v;
+    if (d) {
+      d[i] = dr;
+      d[Np + i] = ds;
+      d[2 * Np + i] = dt;
+    }
+  }
+}
+
+}  // namespace
+
+std::string build_quadrature(const RefOps& ops, QuadOps& Q) {
+  const int N = ops.N, Np = ops.Np, n = N + 1;
+  Q.N = N;
+  Q.Np = Np;
+  // M^-1 of the nodal basis: V V^T (V the orthonormal Vandermonde)
+  std::vector<double> V(size_t(Np) * Np);
+  {
+    std::vector<double> Vi = ops.Vinv;
+    if (!invert(Vi, Np)) return "singular Vandermonde inverse";
+    V = Vi;
+  }
+  const std::vector<double> Minv = matmul(V, transpose(V, Np, Np), Np, Np, Np);
+
+  // volume rule: r = (1+a)(1-b)(1-c)/4 - 1, s = (1+b)(1-c)/2 - 1, t = c,
+  // dr ds dt = (1-b)/2 ((1-c)/2)^2 da db dc
+  std::vector<double> xa, wa, xb, wb, xc, wc;
+  gauss_jacobi(n, 0.0, xa, wa);
+  gauss_jacobi(n, 1.0, xb, wb);
+  gauss_jacobi(n, 2.0, xc, wc);
+  Q.Nq = n * n * n;
+  Q.xq.clear();
+  Q.wq.clear();
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k) {
+        const double a = xa[i], b = xb[j], c = xc[k];
+        Q.xq.push_back(0.25 * (1 + a) * (1 - b) * (1 - c) - 1);
+        Q.xq.push_back(0.5 * (1 + b) * (1 - c) - 1);
+        Q.xq.push_back(c);
+        Q.wq.push_back(wa[i] * wb[j] * wc[k] * 0.5 * 0.25);
+      }
+  // face rule: Radon's seven-point rule of degree 5 (>= 2N + 1 for N <= 2),
+  // symmetric under every permutation of the face's vertices, so the two
+  // elements of a face integrate the numerical flux at the same points; as
+  // barycentrics on the face's three vertices, weights for area 2
+  if (N > 2) return "the face rule covers N <= 2";
+  Q.Nfq = 7;
+  std::vector<double> fb = {1.0 / 3, 1.0 / 3, 1.0 / 3};  // [Nfq][3]
+  Q.wf.assign(1, 2.0 * 9.0 / 40.0);
+  const double r15 = std::sqrt(15.0);
+  for (int orbit = 0; orbit < 2; ++orbit) {
+    const double a = orbit == 0 ? (6 - r15) / 21 : (6 + r15) / 21;
+    const double w = orbit == 0 ? (155 - r15) / 1200 : (155 + r15) / 1200;
+    const double b = 1 - 2 * a;
+    const double pts[3][3] = {{b, a, a}, {a, b, a}, {a, a, b}};
+    for (const auto& pt : pts) {
+      fb.insert(fb.end(), pt, pt + 3);
+      Q.wf.push_back(2.0 * w);
+    }
+  }
+  auto bary_to_rst = [](const double lam[4], double rst[3]) {
+    for (int a = 0; a < 3; ++a) rst[a] = 2.0 * lam[a + 1] - 1.0;
+  };
+
+  const int Nq = Q.Nq, Nfq = Q.Nfq;
+  std::vector<double> l(Np), d(3 * size_t(Np));
+  Q.Bv.assign(size_t(Nq) * Np, 0.0);
+  Q.Dw.assign(size_t(3) * Np * Nq, 0.0);
+  for (int q = 0; q < Nq; ++q) {
+    lagrange_at(ops, &Q.xq[size_t(q) * 3], l.data(), d.data());
+    for (int i = 0; i < Np; ++i) Q.Bv[size_t(q) * Np + i] = l[i];
+    for (int a = 0; a < 3; ++a)
+      for (int i = 0; i < Np; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < Np; ++j) acc += Minv[size_t(i) * Np + j] * d[size_t(a) * Np + j];
+        Q.Dw[(size_t(a) * Np + i) * Nq + q] = acc * Q.wq[q];
+      }
+  }
+  Q.Bf.assign(size_t(4) * Nfq * Np, 0.0);
+  Q.Lq.assign(size_t(4) * Np * Nfq, 0.0);
+  Q.xf.assign(size_t(4) * Nfq * 3, 0.0);
+  for (int f = 0; f < 4; ++f)
+    for (int q = 0; q < Nfq; ++q) {
+      double lam[4] = {0, 0, 0, 0}, rst[3];
+      for (int j = 0; j < 3; ++j) lam[kFaceVerts[f][j]] = fb[size_t(q) * 3 + j];
+      bary_to_rst(lam, rst);
+      for (int a = 0; a < 3; ++a) Q.xf[(size_t(f) * Nfq + q) * 3 + a] = rst[a];
+      lagrange_at(ops, rst, l.data(), nullptr);
+      for (int i = 0; i < Np; ++i) Q.Bf[(size_t(f) * Nfq + q) * Np + i] = l[i];
+      for (int i = 0; i < Np; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < Np; ++j) acc += Minv[size_t(i) * Np + j] * l[j];
+        Q.Lq[(size_t(f) * Np + i) * Nfq + q] = acc * Q.wf[q];
+      }
+    }
+  // neighbour's values at my face points: my face vertex j is vertex
+  // kPerms[o][j] of the neighbour's face f2
+  Q.Bnb.assign(size_t(96) * Nfq * Np, 0.0);
+  for (int f = 0; f < 4; ++f)
+    for (int f2 = 0; f2 < 4; ++f2)
+      for (int o = 0; o < 6; ++o)
+        for (int q = 0; q < Nfq; ++q) {
+          double lam[4] = {0, 0, 0, 0}, rst[3];
+          for (int j = 0; j < 3; ++j) lam[kFaceVerts[f2][kPerms[o][j]]] = fb[size_t(q) * 3 + j];
+          bary_to_rst(lam, rst);
+          lagrange_at(ops, rst, l.data(), nullptr);
+          for (int i = 0; i < Np; ++i)
+            Q.Bnb[((size_t((f * 4 + f2) * 6 + o)) * Nfq + q) * Np + i] = l[i];
+        }
+  return "";
+}
+
 }  // namespace dg

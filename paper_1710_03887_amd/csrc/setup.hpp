@@ -48,6 +48,29 @@ void node_coordinates(const RefOps& ops, const HostMesh& mesh, double* out);
 // Neighbour node map [K][4][Nfp] (k'*Np + node, or -1).
 void neighbour_map(const RefOps& ops, const HostMesh& mesh, int64_t* out);
 
+// Operators of the weak form with Gauss quadrature (Appendix A: volume
+// integrals with a rule exact to degree 2N, face integrals exact to degree
+// 2N + 1), acting on the nodal values of the order-N nodes:
+//   dq/dt = sum_a Dw_a Fc_a(q at the volume points)
+//           - sum_f Fscale_f Lq_f (F* . n)(q at the face points of f),
+// Fc_a the contravariant fluxes.  Rules: inside, the collapsed-coordinate
+// Gauss-Jacobi product with N + 1 points per direction; on faces Radon's
+// symmetric seven-point rule (degree 5, N <= 2).
+struct QuadOps {
+  int N = 0, Np = 0, Nq = 0, Nfq = 0;
+  std::vector<double> Bv;   // [Nq][Np]     nodal values -> volume points
+  std::vector<double> Dw;   // [3][Np][Nq]  M^-1 (d l_i / d r_a)(x_q) w_q
+  std::vector<double> Bf;   // [4][Nfq][Np] nodal values -> face points of face f
+  std::vector<double> Lq;   // [4][Np][Nfq] M^-1 l_i(x_fq) w_fq
+  // [((f*4 + f2)*6 + o)][Nfq][Np]: the neighbour's nodal values -> my face
+  // points, when its face is f2 and o the orientation code
+  std::vector<double> Bnb;
+  std::vector<double> xq, wq;     // volume points [Nq][3] (reference) and weights
+  std::vector<double> xf, wf;     // face points [4][Nfq][3] (reference) and weights [Nfq]
+};
+
+std::string build_quadrature(const RefOps& ops, QuadOps& q);
+
 // Element containing the physical point x: the element whose smallest
 // barycentric coordinate at x is largest (first such element on ties), or -1
 // when that coordinate is below -tol (the point lies outside the mesh).

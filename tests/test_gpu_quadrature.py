@@ -1,0 +1,127 @@
+"""The quadrature scheme (DG_SETUP_QUADRATURE: weak form with Gauss
+quadrature, RK2) on the GPU against its FP64 oracle (oracle/quadrature.py),
+with the bars of the nodal scheme: 2e-5 relative L2 for one right-hand side,
+1e-5 for p' after 100 steps; free stream to FP32 rounding."""
+import numpy as np
+import pytest
+
+import paper_1710_03887_amd as dg
+from oracle import euler, norms
+from oracle.mesh import Mesh
+from oracle.quadrature import QuadScheme
+from workloads import (box_kuhn, trumpet_domain, gaussian_pulse, BC_OUTFLOW_CHAR, BC_WALL,
+                       BC_INFLOW, BC_PASSTHRU)
+from helpers import ref_of, node_perm, phys_kwargs, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+class QPair:
+    def __init__(self, m, N, phys):
+        self.ref = ref_of(N)
+        self.mesh = Mesh(self.ref, m["xyz"], m["EToV"], m["bc"])
+        self.phys = phys
+        self.scheme = QuadScheme(self.mesh)
+        self.ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, quadrature=True,
+                                    **phys_kwargs(phys))
+        self.perm = node_perm(self.ctx, self.ref)
+
+    def to_device(self, q):
+        qp = (q - self.phys.q0[None, :, None])[:, :, self.perm]
+        return torch.tensor(qp, dtype=torch.float32, device="cuda").contiguous()
+
+    def from_device(self, x, perturbation=True):
+        a = x.double().cpu().numpy()
+        out = np.empty_like(a)
+        out[:, :, self.perm] = a
+        return out + self.phys.q0[None, :, None] if perturbation else out
+
+
+def _state(pair, amp=0.1, width=0.4, center=(0.1, -0.05, 0.02), flow=0.03):
+    phys = pair.phys
+    prim = gaussian_pulse(pair.mesh.x, amp * phys.p0, width, center, phys.rho0, phys.p0, phys.gamma)
+    prim[..., 1] += flow * np.sin(np.pi * pair.mesh.x[..., 1])
+    return euler.initial_state(prim, phys.gamma)
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_rhs_parity_all_boundary_kinds(N):
+    phys = euler.Physics(u0=(0.05, -0.02, 0.01), amp=0.1 / 1.4, alpha=10.35)
+    bc = {"x-": BC_INFLOW, "x+": BC_PASSTHRU, "y-": BC_WALL, "y+": BC_WALL,
+          "z-": BC_OUTFLOW_CHAR, "z+": BC_OUTFLOW_CHAR}
+    pair = QPair(box_kuhn((4, 3, 3), jitter=0.05, seed=11, bc=bc), N, phys)
+    q = _state(pair, 0.05, 0.5)
+    rd = torch.full_like(pair.to_device(q), float("nan"))
+    dg.dg_rhs(pair.ctx, pair.to_device(q), rd, 0.13)
+    torch.cuda.synchronize()
+    r_or = pair.scheme.rhs(q, 0.13, phys)
+    err = rel_l2(pair.mesh, pair.from_device(rd, perturbation=False), r_or)
+    print(f"N={N} quadrature rhs rel L2 {err:.3e}")
+    assert err < 2e-5
+    # it is not the nodal scheme's right-hand side
+    assert rel_l2(pair.mesh, r_or, euler.rhs(pair.mesh, q, 0.13, phys)) > 1e-4
+
+
+def test_rhs_parity_trumpet_n2():
+    phys = euler.Physics(amp=0.1 / 1.4)
+    pair = QPair(trumpet_domain("box", 2500), 2, phys)
+    q = _state(pair, 0.05, 0.3, (0.9, 0.05, 0.0), 0.02)
+    rd = torch.empty_like(pair.to_device(q))
+    dg.dg_rhs(pair.ctx, pair.to_device(q), rd, 0.2)
+    torch.cuda.synchronize()
+    err = rel_l2(pair.mesh, pair.from_device(rd, perturbation=False), pair.scheme.rhs(q, 0.2, phys))
+    print(f"trumpet N=2 quadrature rhs rel L2 {err:.3e}")
+    assert err < 2e-5
+
+
+def test_free_stream():
+    phys = euler.Physics(u0=(0.2, -0.1, 0.05))
+    pair = QPair(box_kuhn(3, jitter=0.08, seed=1), 2, phys)
+    q = torch.zeros((pair.ctx.K, 5, pair.ctx.Np), device="cuda")
+    rd = torch.empty_like(q)
+    dg.dg_rhs(pair.ctx, q, rd, 0.0)
+    torch.cuda.synchronize()
+    assert float(rd.abs().max()) < 1e-6
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_run_parity_100_steps(N):
+    phys = euler.Physics()
+    pair = QPair(box_kuhn(4, jitter=0.05, seed=9), N, phys)
+    q0 = _state(pair, 0.1, 0.25, (0.0, 0.0, 0.0), 0.0)
+    q_or, t_or, dts = pair.scheme.run(q0, phys, 100, cfl=0.3)
+    qd = pair.to_device(q0)
+    res = torch.zeros_like(qd)
+    t, dt_last = dg.dg_run(pair.ctx, qd, res, 100, 0.3, 0.0)
+    assert abs(t / t_or - 1) < 1e-6 and abs(dt_last / dts[-1] - 1) < 1e-6
+    err = norms.rel_l2_pressure(pair.mesh, pair.from_device(qd), q_or, phys)
+    print(f"N={N} quadrature scheme, 100 RK2 steps: p' rel L2 {err:.3e}")
+    assert err < 1e-5
+    # one dg_step equals one oracle RK2 step
+    qd = pair.to_device(q0)
+    dg.dg_step(pair.ctx, qd, res, 0.0, dts[0])
+    torch.cuda.synchronize()
+    q1 = pair.scheme.rk2_step(q0, 0.0, dts[0], phys)
+    assert norms.rel_l2_pressure(pair.mesh, pair.from_device(qd), q1, phys) < 1e-5
+
+
+def test_scheme_restrictions():
+    phys = euler.Physics()
+    m = box_kuhn(2)
+    with pytest.raises(dg.DGError):
+        dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], 3, quadrature=True)
+    with pytest.raises(dg.DGError):
+        dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], 2, quadrature=True, precision=dg.DG_SPLIT_BF16)
+    pair = QPair(m, 2, phys)
+    q = torch.zeros((pair.ctx.K, 5, pair.ctx.Np), device="cuda")
+    with pytest.raises(dg.DGError):
+        dg.dg_stage(pair.ctx, q, torch.empty_like(q), torch.zeros_like(q), 0.0, 1.0, 0.0, 0.01)
+    with pytest.raises(dg.DGError):
+        dg.dg_set_kernel(pair.ctx, 1)
+    with pytest.raises(dg.DGError):
+        dg.dg_set_damping(pair.ctx, torch.zeros((pair.ctx.K, pair.ctx.Np), device="cuda"))
+    with pytest.raises(dg.DGError):
+        dg.dg_batch_create([pair.ctx], 4)
+    assert dg.dg_autotune(pair.ctx, q, torch.zeros_like(q)) == 0
