@@ -263,6 +263,49 @@ def time_probes(dg, torch, m, steps=200):
             "max_abs_p_prime": float(series.abs().max())}
 
 
+def time_quadrature(dg, torch, m, steps=200):
+    """The paper's own discretization (weak form with Gauss quadrature, RK2)
+    on the c2 trumpet at N = 1 (the order the paper ran) and N = 2: dg_run
+    throughput and the per-stage kernel time (a step is two stages)."""
+    amp, alpha, p0 = 0.1 / 1.4, 2 * np.pi * 565.0 / 343.0, 1.0 / 1.4
+    out = {}
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    for N in (1, 2):
+        ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, gamma=1.4, rho0=1.0, p0=p0,
+                               inflow_amp=amp, inflow_alpha=alpha, quadrature=True)
+        K, Np = ctx.K, ctx.Np
+        q = torch.zeros((K, 5, Np), dtype=torch.float32, device=dev)
+        res = torch.zeros_like(q)
+        t, _ = dg.dg_run(ctx, q, res, 10, 0.3, 0.0, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        t, dt_last = dg.dg_run(ctx, q, res, steps, 0.3, t, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        # stage kernel alone: one right-hand side per launch in MODE_RHS
+        r = torch.empty_like(q)
+        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(3):
+            dg.dg_rhs(ctx, q, r, t, stream=stream)
+        k0.record(stream)
+        for _ in range(20):
+            dg.dg_rhs(ctx, q, r, t, stream=stream)
+        k1.record(stream)
+        torch.cuda.synchronize()
+        rhs_ms = k0.elapsed_time(k1) / 20
+        # an RK2 stage moves on average 2.5 FP32 state passes plus geometry
+        nbytes = K * (50 * Np + 220)
+        out[f"N{N}"] = {"K": K, "Np": Np, "steps": steps, "ms_per_step": ms / steps,
+                        "value": 5 * K * Np * 2 * steps / (ms * 1e-3), "dt_last": dt_last,
+                        "rhs_kernel_ms": rhs_ms,
+                        "stage_GBs": nbytes / (ms / steps / 2 * 1e-3) / 1e9}
+        dg.dg_destroy(ctx)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,9 +315,9 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--form", choices=("fp32", "bf16"), default="fp32",
                     help="form of the headline measurement")
-    ap.add_argument("--also", default="bf16,batch,n5,probes",
-                    help="comma list of extra measurements: bf16, fp32, batch, n5, probes "
-                         "(or empty)")
+    ap.add_argument("--also", default="bf16,batch,n5,probes,quadrature",
+                    help="comma list of extra measurements: bf16, fp32, batch, n5, probes, "
+                         "quadrature (or empty)")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--n5-steps", type=int, default=100,
                     help="steps per form of the 1.17M-tet N = 5 precision workload")
@@ -314,6 +357,8 @@ def main():
             extra["n5"] = time_precision_n5(dg, torch, args.n5_steps)
         elif name == "probes":
             extra["probes"] = time_probes(dg, torch, m)
+        elif name == "quadrature":
+            extra["quadrature"] = time_quadrature(dg, torch, m)
     if args.copy_mb:
         n = args.copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
