@@ -190,7 +190,7 @@ def outer_domains(scene, amp, t_end, dt, configs, every=100):
     """Interior error on outer boxes `scale` times the small box (each
     containing the small mesh element for element), closed by the
     characteristic ghost, with an absorbing layer of peak rate sigma_max in
-    the shell around the small box when sigma_max > 0; judged like
+    the shell around the small box when sigma_max > 0; measured like
     reflection_error against the scene's larger domain on the small box's
     elements.  configs: [(scale, sigma_max)].  Returns ([error], [seconds per
     step], [elements]) per config."""
@@ -199,7 +199,7 @@ def outer_domains(scene, amp, t_end, dt, configs, every=100):
     big = scene.context("big", amp)
     runs, maps, keep = [], [], []
     for sc, smax in configs:
-        if sc == 1.0:   # the small box itself (a layer then lies inside it: not judged fairly)
+        if sc == 1.0:   # the small box itself (a layer then lies inside it: not a fair comparison)
             if smax > 0:
                 raise ValueError("an absorbing layer needs an outer box larger than the small box")
             mid, emap = scene.small, np.arange(len(scene.small["EToV"]))

@@ -4,7 +4,7 @@ trained on them by the library's kernels, its blend toward the
 characteristic ghost picked at one amplitude outside the training set, then
 the truncated box run with either ghost in lockstep with the larger domain
 at another such amplitude.  The learned ghost must leave a smaller interior
-reflection error (the larger domain's solution is the judge).  Amplitudes
+reflection error (the larger domain's solution is the reference).  Amplitudes
 stay at or below 3% of p0: without a limiter, stronger pulses steepen into
 shocks in the bore on these coarse meshes and the solution breaks down.
 
@@ -41,7 +41,7 @@ def test_learned_closure_beats_characteristic():
     blend, table, _ = lb.choose_blend(scene, net, win, 0.007 * lb.P0, t_end, dt,
                                       blends=(0.5, 0.75, 1.0))
     print("blend", blend, table, flush=True)
-    # ... and judged at another
+    # ... and evaluated at another
     errs, secs = lb.reflection_error(scene, 0.02 * lb.P0, t_end, dt, nets=[net], window=win,
                                      blends=[blend])
     print(f"interior reflection error: char {errs[0]:.4e}, learned {errs[1]:.4e} "
