@@ -136,12 +136,23 @@ def time_single(dg, torch, m, N, form, steps, warmup, kernel_iters):
     k1.record(stream)
     torch.cuda.synchronize()
     kernel_s = k0.elapsed_time(k1) * 1e-3 / kernel_iters
+    # dg_rhs alone (q in, rhs out: 40 Np + 220 algorithmic bytes per element)
+    r = torch.empty_like(q)
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r0.record(stream)
+    for _ in range(kernel_iters):
+        dg.dg_rhs(ctx, q, r, t_end, stream=stream)
+    r1.record(stream)
+    torch.cuda.synchronize()
+    rhs_s = r0.elapsed_time(r1) * 1e-3 / kernel_iters
+    rhs_bytes = K * (40 * Np + 220)
     nbytes = stage_bytes(K, Np, True)
     variant = dg.dg_get_kernel(ctx)
     return {"K": K, "N": N, "Np": Np, "dof": dof, "ms": ms, "wall_s": wall, "t_end": t_end,
             "dt_last": dt_last, "value": dof * 5 * steps / (ms * 1e-3), "kernel_s": kernel_s,
             "bytes": nbytes, "achieved": nbytes / kernel_s / 1e9, "blocks_per_cu": bpc,
             "kernel_variant": variant,
+            "rhs_ms": rhs_s * 1e3, "rhs_GBs": rhs_bytes / rhs_s / 1e9,
             "kernel": ("stage_kernel" if variant == 0 else "wave_stage_kernel") +
                       f"<{N},MODE_STAGE>"}
 
@@ -390,7 +401,10 @@ def main():
                      "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
                                      "copy-calibrated)",
                      "kernel": r["kernel"], "kernel_ms": r["kernel_s"] * 1e3,
-                     "bytes_per_launch": r["bytes"]},
+                     "bytes_per_launch": r["bytes"],
+                     "dg_rhs": {"ms": r["rhs_ms"], "achieved": r["rhs_GBs"],
+                                "frac": r["rhs_GBs"] / HBM_PEAK_GBS,
+                                "bytes_per_launch": r["K"] * (40 * r["Np"] + 220)}},
         "forms": extra,
     }
     if not args.no_cpu_baseline:

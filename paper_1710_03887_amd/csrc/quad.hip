@@ -41,6 +41,39 @@ struct QShape {
   static constexpr int total = oBnb + 96 * Nfq * Np;
 };
 
+// An element's ST contiguous floats with the widest vector accesses its
+// alignment allows (element blocks of 80 B at N = 1, 200 B at N = 2).
+template <int ST>
+struct ElemIO {
+  static constexpr int W = (ST * 4) % 16 == 0 ? 4 : ((ST * 4) % 8 == 0 ? 2 : 1);
+  __device__ static __forceinline__ void load(const float* p, float (&x)[ST]) {
+#pragma unroll
+    for (int j = 0; j < ST / W; ++j) {
+      if constexpr (W == 4) {
+        const float4 v = reinterpret_cast<const float4*>(p)[j];
+        x[4 * j] = v.x; x[4 * j + 1] = v.y; x[4 * j + 2] = v.z; x[4 * j + 3] = v.w;
+      } else if constexpr (W == 2) {
+        const float2 v = reinterpret_cast<const float2*>(p)[j];
+        x[2 * j] = v.x; x[2 * j + 1] = v.y;
+      } else {
+        x[j] = p[j];
+      }
+    }
+  }
+  __device__ static __forceinline__ void store(float* p, const float (&x)[ST]) {
+#pragma unroll
+    for (int j = 0; j < ST / W; ++j) {
+      if constexpr (W == 4) {
+        reinterpret_cast<float4*>(p)[j] = make_float4(x[4 * j], x[4 * j + 1], x[4 * j + 2], x[4 * j + 3]);
+      } else if constexpr (W == 2) {
+        reinterpret_cast<float2*>(p)[j] = make_float2(x[2 * j], x[2 * j + 1]);
+      } else {
+        p[j] = x[j];
+      }
+    }
+  }
+};
+
 __device__ __forceinline__ double stage_time(double c, double t_host, double dt_host,
                                              const RunScalars* run) {
   if (run) return run->t + c * run->dt;
@@ -76,13 +109,17 @@ __global__ __launch_bounds__(256) void quad_kernel(DeviceMesh m, const float* __
   for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < m.K;
        k += int64_t(gridDim.x) * blockDim.x) {
     float qe[5][Np], acc[5][Np];
+    {
+      float flat[ST];
+      ElemIO<ST>::load(q_in + k * ST, flat);
 #pragma unroll
-    for (int v = 0; v < 5; ++v)
+      for (int v = 0; v < 5; ++v)
 #pragma unroll
-      for (int i = 0; i < Np; ++i) {
-        qe[v][i] = q_in[k * ST + v * Np + i];
-        acc[v][i] = 0.0f;
-      }
+        for (int i = 0; i < Np; ++i) {
+          qe[v][i] = flat[v * Np + i];
+          acc[v][i] = 0.0f;
+        }
+    }
     float G[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) G[i] = float(m.vgeo[k * 9 + i]);
@@ -126,10 +163,12 @@ __global__ __launch_bounds__(256) void quad_kernel(DeviceMesh m, const float* __
       float qn[5][Np];
       const float* Bn = T;
       if (nb >= 0) {
+        float flat[ST];
+        ElemIO<ST>::load(q_in + int64_t(nb) * ST, flat);
 #pragma unroll
         for (int v = 0; v < 5; ++v)
 #pragma unroll
-          for (int i = 0; i < Np; ++i) qn[v][i] = q_in[int64_t(nb) * ST + v * Np + i];
+          for (int i = 0; i < Np; ++i) qn[v][i] = flat[v * Np + i];
         const int fi = m.finfo[k * 4 + f];
         Bn = T + S::oBnb + ((f * 4 + (fi & 3)) * 6 + (fi >> 2)) * Nfq * Np;
       } else {
@@ -185,20 +224,29 @@ __global__ __launch_bounds__(256) void quad_kernel(DeviceMesh m, const float* __
 
     // epilogue
     if (MODE == MODE_RHS) {
+      float flat[ST];
 #pragma unroll
       for (int v = 0; v < 5; ++v)
 #pragma unroll
-        for (int i = 0; i < Np; ++i) out[k * ST + v * Np + i] = acc[v][i];
+        for (int i = 0; i < Np; ++i) flat[v * Np + i] = acc[v][i];
+      ElemIO<ST>::store(out + k * ST, flat);
     } else {
+      float flat[ST];
+      if (alpha != 0.0f) {
+        ElemIO<ST>::load(q_base + k * ST, flat);
+      } else {
+#pragma unroll
+        for (int j = 0; j < ST; ++j) flat[j] = 0.0f;
+      }
 #pragma unroll
       for (int v = 0; v < 5; ++v)
 #pragma unroll
         for (int i = 0; i < Np; ++i) {
-          const float base = alpha != 0.0f ? q_base[k * ST + v * Np + i] : 0.0f;
-          const float qn_ = alpha * base + beta * (qe[v][i] + dt * acc[v][i]);
-          q_out[k * ST + v * Np + i] = qn_;
+          const float qn_ = alpha * flat[v * Np + i] + beta * (qe[v][i] + dt * acc[v][i]);
+          flat[v * Np + i] = qn_;
           qe[v][i] = qn_;
         }
+      ElemIO<ST>::store(q_out + k * ST, flat);
       if (rate_out) {  // next step's CFL rate from the new state's face nodes
 #pragma unroll 1
         for (int f = 0; f < 4; ++f) {
