@@ -114,7 +114,7 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef __attribute__((address_space(1))) void* gvoid_ptr_t;
 
 template <int N, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(3))) void batch_stage_kernel(BatchLaunch L, float a_rk,
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(4))) void batch_stage_kernel(BatchLaunch L, float a_rk,
                                                                  float b_rk, double c_rk,
                                                                  int parity, int rate_out) {
   using S = BShape<N>;
@@ -239,10 +239,8 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(3)))
         }
       }
     };
-    float trn[QF][5];
-    gather(0, trn);
     if constexpr (STAGE) {
-      __builtin_amdgcn_s_waitcnt(0);   // the staged state (and face 0's traces) have landed
+      __builtin_amdgcn_s_waitcnt(0);   // the staged state has landed
       wave_sync();
     }
 
@@ -285,18 +283,16 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(3)))
         }
     }
 
-    // faces one at a time, the next face's traces in flight meanwhile: the
-    // face's Lax-Friedrichs speed per member (max over its nodes and both
-    // sides, reduced over the four lane groups), then the jump
+    // faces one at a time (the exterior traces gathered per face: the kernel
+    // runs four wavefronts per SIMD, which hide the gathers' latency better
+    // than a register prefetch that would cost that occupancy): the face's
+    // Lax-Friedrichs speed per member (max over its nodes and both sides,
+    // reduced over the four lane groups), then the jump
     // Fscale/2 [n.(F- - F+) - lambda (q- - q+)] against the LIFT rows
 #pragma unroll 1
     for (int f = 0; f < 4; ++f) {
       float trc[QF][5];
-#pragma unroll
-      for (int q = 0; q < QF; ++q)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) trc[q][v] = trn[q][v];
-      if (f < 3) gather(f + 1, trn);
+      gather(f, trc);
       const float n[3] = {pick4b(nx, f), pick4b(ny, f), pick4b(nz, f)};
       const int nb = pick4b(nbr, f);
       // the face's traces on both sides (recomputed in the two sub-passes
