@@ -392,6 +392,37 @@ int dg_sample_traces(dg_ctx* ctx, const float* q, const int64_t* faces, int64_t 
  * DG_ENODEV on a host-only context. */
 int dg_set_damping(dg_ctx* ctx, const float* sigma);
 
+/* ---- curved (isoparametric) elements -----------------------------------
+ * Section 3 ascribes the reflections of the spherical outer domain to its
+ * boundary being built from flat faces; curved boundary elements are the
+ * remedy it names.  xyz_nodes (host FP64 [K][Np][3], the library's node
+ * order, see dg_nodes and dg_reference_operators) gives the physical
+ * position of every node; each element's map becomes the degree-N
+ * polynomial through its nodes.  Elements whose nodes lie within tol times
+ * their longest edge of the straight-sided positions stay straight; for the
+ * others ("curved") the library keeps, at every node, the metric terms
+ * d(r,s,t)/d(x,y,z) of that map and, at every face node, the outward unit
+ * normal and sJ/J, and evaluates their right-hand side as
+ *   dq/dt(node n) = - sum_a sum_d (d r_a/d x_d)(n) (D_a F_d)(n)
+ *                   + sum_f LIFT_f [ (sJ/J) dF ]_f,
+ * (the volume term in chain-rule form, which is the straight-sided operator
+ * when the metric terms are constant; dF the local Lax-Friedrichs jump with
+ * each face node's own normal, one lambda per face).  The time-step rule
+ * keeps each element's straight-sided Fscale.  Curved elements are computed
+ * by a separate pass after the stage kernel (which also writes them), so the
+ * straight elements keep the full-speed path.  Copies what it needs; the
+ * host array may be freed on return.  NULL clears the curved set.  Applies
+ * to dg_rhs, dg_step, dg_stage, the runs and dg_autotune of this context;
+ * probes locate their points with the straight-sided geometry.
+ * n_curved_out (may be NULL) receives the number of curved elements.
+ * Errors: DG_EINVAL for tol <= 0, a context with the quadrature scheme or a
+ * learned closure, a node Jacobian <= 0, or node positions that do not
+ * coincide (to tol times the edge length) on a shared face; DG_ENODEV on a
+ * host-only context; DG_ENOMEM / DG_EHIP.  dg_batch_create and
+ * dg_set_learned_bc reject a context with curved elements.  Synchronous. */
+int dg_set_curved(dg_ctx* ctx, const double* xyz_nodes, double tol, int64_t* n_curved_out,
+                  void* stream);
+
 /* ---- pressure probes and spectra -----------------------------------------
  * Section 3 samples the pressure of each run at sensor points inside and
  * around the instrument and compares the frequency content of those signals

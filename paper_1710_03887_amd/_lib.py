@@ -88,6 +88,7 @@ _SIGS = {
     "dg_learned_faces": (_i64, [_vp, _vp]),
     "dg_sample_traces": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, _vp, _vp, _vp]),
     "dg_set_damping": (ctypes.c_int, [_vp, _vp]),
+    "dg_set_curved": (ctypes.c_int, [_vp, _vp, _f64, ctypes.POINTER(_i64), _vp]),
     "dg_probe_setup": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
     "dg_probe_sample": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "dg_run_probes": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f64, ctypes.POINTER(_f64), _vp, _vp]),
@@ -435,6 +436,22 @@ def dg_set_damping(ctx, sigma):
         _check_device_f32(sigma, (ctx.K, ctx.Np), "sigma")
     _check(_lib.dg_set_damping(ctx.handle, _ptr(sigma)), ctx.handle)
     ctx.sigma = sigma   # keeps the tensor alive with the context
+
+
+def dg_set_curved(ctx, xyz_nodes, tol=1e-9, stream=None):
+    """Curved node positions (host float64 [K, Np, 3], library node order)
+    or None to clear; returns the number of curved elements."""
+    n = _i64(0)
+    if xyz_nodes is None:
+        _check(_lib.dg_set_curved(ctx.handle, None, float(tol), ctypes.byref(n), _stream(stream)),
+               ctx.handle)
+        return 0
+    x = np.ascontiguousarray(xyz_nodes, dtype=np.float64)
+    if x.shape != (ctx.K, ctx.Np, 3):
+        raise ValueError(f"xyz_nodes must have shape {(ctx.K, ctx.Np, 3)}")
+    _check(_lib.dg_set_curved(ctx.handle, _ptr(x), float(tol), ctypes.byref(n), _stream(stream)),
+           ctx.handle)
+    return int(n.value)
 
 
 # ---- pressure probes and spectra -----------------------------------------------------

@@ -54,9 +54,16 @@ void free_probes(dg_ctx* c) {
   c->probe_host = dg::ProbeSet{};
 }
 
+void free_curved(dg_ctx* c) {
+  for (void* p : c->curved_allocs) (void)hipFree(p);
+  c->curved_allocs.clear();
+  c->curved = dg::CurvedSet{};
+}
+
 void free_device(dg_ctx* c) {
   drop_graphs(c);
   free_probes(c);
+  free_curved(c);
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -180,7 +187,19 @@ hipError_t stage(dg_ctx* c, int mode, const float* q_in, float* q_out, float* re
     if (e == hipSuccess) e = dg::launch_learned_ghost(c->dm, c->lbc, q_in, s);
     if (e != hipSuccess) return e;
   }
-  return dg::launch_stage(c->dm, mode, q_in, q_out, res, out, a, b, cc, t, dt, run, rate_out, s);
+  if (c->curved.n == 0)
+    return dg::launch_stage(c->dm, mode, q_in, q_out, res, out, a, b, cc, t, dt, run, rate_out, s);
+  // curved elements: their residual is kept before the stage kernel
+  // overwrites it, then their own pass replaces what the stage kernel wrote
+  // for them, and the time-step rate is reduced from the finished state
+  hipError_t e = hipSuccess;
+  if (mode == dg::MODE_STAGE && a != 0.0f) e = dg::launch_curved_save(c->curved, c->dm, res, s);
+  if (e == hipSuccess)
+    e = dg::launch_stage(c->dm, mode, q_in, q_out, res, out, a, b, cc, t, dt, run, 0, s);
+  if (e == hipSuccess)
+    e = dg::launch_curved(c->curved, c->dm, mode, q_in, q_out, res, out, a, b, cc, t, dt, run, s);
+  if (e == hipSuccess && run && rate_out) e = dg::launch_rate(c->dm, q_out, run, s);
+  return e;
 }
 
 // Enqueue one LSERK step on `s` with state ping-ponging between q and the
@@ -562,6 +581,64 @@ int dg_set_damping(dg_ctx* c, const float* sigma) {
   if (c->dm.scheme == 1 && sigma) return fail(c, DG_EINVAL, "no absorbing layer in the quadrature scheme");
   c->dm.sigma = sigma;
   drop_graphs(c);
+  return DG_OK;
+}
+
+int dg_set_curved(dg_ctx* c, const double* xyz_nodes, double tol, int64_t* n_curved_out,
+                  void* stream) {
+  int rc = need_device(c);
+  if (rc) return rc;
+  if (n_curved_out) *n_curved_out = 0;
+  drop_graphs(c);
+  free_curved(c);
+  if (!xyz_nodes) return DG_OK;
+  if (!(tol > 0.0)) return fail(c, DG_EINVAL, "tol must be positive");
+  if (c->dm.scheme == 1) return fail(c, DG_EINVAL, "no curved elements in the quadrature scheme");
+  if (c->mlp) return fail(c, DG_EINVAL, "curved elements and a learned closure do not combine");
+  std::vector<int64_t> elems;
+  std::vector<float> vg, sg;
+  const std::string msg = dg::curved_geometry(c->ops, c->mesh, xyz_nodes, tol, elems, vg, sg);
+  if (!msg.empty()) return fail(c, DG_EINVAL, msg);
+  const int64_t n = int64_t(elems.size());
+  if (n == 0) return DG_OK;
+  const int Np = c->ops.Np, NF = 4 * c->ops.Nfp;
+  std::vector<float> D(size_t(3) * Np * Np), L(size_t(Np) * NF);
+  for (size_t i = 0; i < size_t(Np) * Np; ++i) {
+    D[i] = float(c->ops.Dr[i]);
+    D[size_t(Np) * Np + i] = float(c->ops.Ds[i]);
+    D[size_t(2) * Np * Np + i] = float(c->ops.Dt[i]);
+  }
+  for (size_t i = 0; i < L.size(); ++i) L[i] = float(c->ops.LIFT[i]);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* p[6] = {};
+  const size_t bytes[6] = {size_t(n) * sizeof(int64_t), vg.size() * sizeof(float),
+                           sg.size() * sizeof(float), D.size() * sizeof(float),
+                           L.size() * sizeof(float), size_t(n) * 5 * Np * sizeof(float)};
+  const void* src[6] = {elems.data(), vg.data(), sg.data(), D.data(), L.data(), nullptr};
+  for (int i = 0; i < 6; ++i) {
+    const hipError_t e = hipMalloc(&p[i], bytes[i]);
+    if (e != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipFree(p[j]);
+      return fail(c, DG_ENOMEM, "hipMalloc for curved elements");
+    }
+  }
+  for (int i = 0; i < 6; ++i) c->curved_allocs.push_back(p[i]);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 5 && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(p[i], src[i], bytes[i], hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors end here
+  if (e != hipSuccess) {
+    free_curved(c);
+    return hip_fail(c, e, "curved element upload");
+  }
+  c->curved.n = n;
+  c->curved.elem = static_cast<const int64_t*>(p[0]);
+  c->curved.vg = static_cast<const float*>(p[1]);
+  c->curved.sg = static_cast<const float*>(p[2]);
+  c->curved.D = static_cast<const float*>(p[3]);
+  c->curved.L = static_cast<const float*>(p[4]);
+  c->curved.res_save = static_cast<float*>(p[5]);
+  if (n_curved_out) *n_curved_out = n;
   return DG_OK;
 }
 

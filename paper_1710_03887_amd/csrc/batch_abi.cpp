@@ -51,7 +51,8 @@ int dg_batch_create(dg_ctx* const* geoms, int ngeom, int members, void* stream, 
   *out = nullptr;
   if (!geoms || ngeom < 1 || ngeom > 64 || members < 1 || members > dg::kMembers) return DG_EINVAL;
   for (int g = 0; g < ngeom; ++g)  // the batched kernel has no absorbing layer
-    if (!geoms[g] || geoms[g]->host_only || geoms[g]->dm.sigma || geoms[g]->dm.scheme != 0)
+    if (!geoms[g] || geoms[g]->host_only || geoms[g]->dm.sigma || geoms[g]->dm.scheme != 0 ||
+        geoms[g]->curved.n != 0)
       return DG_EINVAL;
   const dg_ctx* c0 = geoms[0];
   for (int g = 1; g < ngeom; ++g) {

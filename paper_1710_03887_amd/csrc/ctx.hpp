@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "batch.hpp"
+#include "curved.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
 #include "probes.hpp"
@@ -65,6 +66,8 @@ struct dg_ctx {
   int64_t* probe_elem = nullptr;    // device [n]
   float* probe_w = nullptr;         // device [n][Np]
   int64_t last_bad = -1;
+  dg::CurvedSet curved;             // curved elements (n = 0: none)
+  std::vector<void*> curved_allocs;
 };
 
 // Captured step graphs are rebuilt after anything they bake in changes

@@ -1,0 +1,35 @@
+// Curved (isoparametric) elements: per-node metric terms and per-face-node
+// normals for the elements whose map is not affine, and the pass that
+// evaluates their right-hand side after the stage kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace dg {
+
+struct CurvedSet {
+  int64_t n = 0;                 // curved elements
+  const int64_t* elem = nullptr; // [n] element ids, ascending
+  const float* vg = nullptr;     // [n][Np][9] d r_a / d x_d at each node
+  const float* sg = nullptr;     // [n][4][Nfp][4] unit normal, sJ/J at each face node
+  const float* D = nullptr;      // [3][Np][Np] Dr, Ds, Dt (row-major)
+  const float* L = nullptr;      // [Np][4 Nfp] LIFT
+  float* res_save = nullptr;     // [n][5][Np] their residual before the stage kernel
+};
+
+// res_save[c] = res[elem[c]] (before a stage kernel overwrites them).
+hipError_t launch_curved_save(const CurvedSet& cv, const DeviceMesh& m, const float* res,
+                              hipStream_t s);
+
+// The curved elements' share of one right-hand side or LSERK stage, with the
+// contract of launch_stage (MODE_RHS: out = f(q_in); MODE_STAGE:
+// res = a res_save + dt f(q_in), q_out = q_in + b res); no rate reduction.
+hipError_t launch_curved(const CurvedSet& cv, const DeviceMesh& m, int mode, const float* q_in,
+                         float* q_out, float* res, float* out, float a, float b, double c,
+                         double t_host, double dt_host, const RunScalars* run, hipStream_t s);
+
+}  // namespace dg

@@ -199,6 +199,10 @@ int dg_set_learned_bc(dg_ctx* c, dg_mlp* m, double norm, double p_lo, double p_h
     c->err = "context was created host-only";
     return DG_ENODEV;
   }
+  if (m && c->curved.n != 0) {
+    c->err = "curved elements and a learned closure do not combine";
+    return DG_EINVAL;
+  }
   if (m && (c->dm.N != 4 || !(norm >= 0.0) || !(p_lo >= 0.0) || !(p_hi >= p_lo) ||
             !(blend >= 0.0 && blend <= 1.0))) {
     c->err = "the learned closure needs N = 4, norm >= 0, 0 <= p_lo <= p_hi, 0 <= blend <= 1";

@@ -564,6 +564,98 @@ void neighbour_map(const RefOps& ops, const HostMesh& m, int64_t* out) {
     }
 }
 
+std::string curved_geometry(const RefOps& ops, const HostMesh& m, const double* x, double tol,
+                            std::vector<int64_t>& elems, std::vector<float>& vg,
+                            std::vector<float>& sg) {
+  const int Np = ops.Np, Nfp = ops.Nfp;
+  elems.clear();
+  vg.clear();
+  sg.clear();
+  std::vector<double> straight(size_t(m.K) * Np * 3);
+  node_coordinates(ops, m, straight.data());
+  std::vector<double> edge(m.K);
+  for (int64_t k = 0; k < m.K; ++k) {
+    const double* X = &m.xyz[size_t(k) * 12];
+    double e2 = 0.0;
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b) {
+        double d2 = 0.0;
+        for (int d = 0; d < 3; ++d) d2 += (X[a * 3 + d] - X[b * 3 + d]) * (X[a * 3 + d] - X[b * 3 + d]);
+        e2 = std::max(e2, d2);
+      }
+    edge[k] = std::sqrt(e2);
+    double dev = 0.0;
+    for (int n = 0; n < Np * 3; ++n) {
+      const double v = x[size_t(k) * Np * 3 + n];
+      if (!std::isfinite(v)) return "non-finite node position";
+      dev = std::max(dev, std::fabs(v - straight[size_t(k) * Np * 3 + n]));
+    }
+    if (dev > tol * edge[k]) elems.push_back(k);
+  }
+  // shared face nodes must coincide
+  for (int64_t k = 0; k < m.K; ++k)
+    for (int f = 0; f < 4; ++f) {
+      const int32_t k2 = m.EToE[k * 4 + f];
+      if (k2 < 0) continue;
+      const int f2 = m.EToF[k * 4 + f], o = m.orient[k * 4 + f];
+      for (int i = 0; i < Nfp; ++i) {
+        const int n1 = ops.Fmask[f * Nfp + i];
+        const int n2 = ops.nbr_node[((size_t(f) * 4 + f2) * 6 + o) * Nfp + i];
+        for (int d = 0; d < 3; ++d)
+          if (std::fabs(x[(size_t(k) * Np + n1) * 3 + d] - x[(size_t(k2) * Np + n2) * 3 + d]) >
+              tol * std::max(edge[k], edge[k2]))
+            return "curved node positions do not coincide on a shared face";
+      }
+    }
+  static const double kGrad[4][3] = {{0, 0, -1}, {0, -1, 0}, {1, 1, 1}, {-1, 0, 0}};
+  const size_t nc = elems.size();
+  vg.resize(nc * Np * 9);
+  sg.resize(nc * 4 * Nfp * 4);
+  std::vector<double> G(size_t(Np) * 9);
+  for (size_t c = 0; c < nc; ++c) {
+    const double* X = x + size_t(elems[c]) * Np * 3;
+    for (int n = 0; n < Np; ++n) {
+      double Jm[3][3];  // Jm[d][a] = d x_d / d r_a
+      const double* D[3] = {&ops.Dr[size_t(n) * Np], &ops.Ds[size_t(n) * Np], &ops.Dt[size_t(n) * Np]};
+      for (int a = 0; a < 3; ++a)
+        for (int d = 0; d < 3; ++d) {
+          double v = 0.0;
+          for (int j = 0; j < Np; ++j) v += D[a][j] * X[j * 3 + d];
+          Jm[d][a] = v;
+        }
+      // inverse by cofactors: G[a][d] = cof(Jm)[d][a] / det
+      const double c00 = Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1];
+      const double c01 = Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2];
+      const double c02 = Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0];
+      const double det = Jm[0][0] * c00 + Jm[0][1] * c01 + Jm[0][2] * c02;
+      if (!(det > 0.0)) return "curved element with a non-positive Jacobian at a node";
+      double* g = &G[size_t(n) * 9];
+      g[0 * 3 + 0] = c00 / det;
+      g[1 * 3 + 0] = c01 / det;
+      g[2 * 3 + 0] = c02 / det;
+      g[0 * 3 + 1] = (Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2]) / det;
+      g[1 * 3 + 1] = (Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0]) / det;
+      g[2 * 3 + 1] = (Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1]) / det;
+      g[0 * 3 + 2] = (Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1]) / det;
+      g[1 * 3 + 2] = (Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2]) / det;
+      g[2 * 3 + 2] = (Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0]) / det;
+      for (int i = 0; i < 9; ++i) vg[(c * Np + n) * 9 + i] = float(g[i]);
+    }
+    for (int f = 0; f < 4; ++f)
+      for (int i = 0; i < Nfp; ++i) {
+        const double* g = &G[size_t(ops.Fmask[f * Nfp + i]) * 9];
+        double nv[3];
+        for (int d = 0; d < 3; ++d)
+          nv[d] = kGrad[f][0] * g[0 * 3 + d] + kGrad[f][1] * g[1 * 3 + d] + kGrad[f][2] * g[2 * 3 + d];
+        const double len = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        float* o = &sg[((c * 4 + f) * Nfp + i) * 4];
+        for (int d = 0; d < 3; ++d) o[d] = float(nv[d] / len);
+        o[3] = float(len);
+      }
+  }
+  return "";
+}
+
 int64_t locate_point(const HostMesh& m, const double x[3], double tol, double rst[3]) {
   int64_t best = -1;
   double best_min = -1e300;

@@ -71,6 +71,21 @@ struct QuadOps {
 
 std::string build_quadrature(const RefOps& ops, QuadOps& q);
 
+// Curved (isoparametric) elements: each element's map is the degree-N
+// polynomial through the given physical positions of its nodes x [K][Np][3]
+// (node order of ops.rst).  An element is curved when one of its nodes lies
+// farther than tol times its longest edge from the straight-sided position.
+// For each curved element (ascending ids in `elems`), at every node:
+//   vg[(c*Np + n)*9 + a*3 + d] = d r_a / d x_d  (inverse of [Dr x, Ds x, Dt x]),
+// and at every face node (face-major, Fmask order):
+//   sg[(c*4*Nfp + f*Nfp + i)*4 + 0..2] = outward unit normal, [3] = sJ / J,
+// the normal being the gradient of the face's reference coordinate
+// (-grad t, -grad s, grad(r+s+t), -grad r for faces 0..3).
+// Fails when a node's Jacobian is not positive or the nodes that two
+// elements share on a face do not coincide (to tol times the edge length).
+std::string curved_geometry(const RefOps& ops, const HostMesh& mesh, const double* x, double tol,
+                            std::vector<int64_t>& elems, std::vector<float>& vg,
+                            std::vector<float>& sg);
 // Element containing the physical point x: the element whose smallest
 // barycentric coordinate at x is largest (first such element on ties), or -1
 // when that coordinate is below -tol (the point lies outside the mesh).
