@@ -317,6 +317,49 @@ def time_quadrature(dg, torch, m, steps=200):
     return out
 
 
+def time_curved(dg, torch, steps=100, target_K=80_000, N=4):
+    """The spherical trumpet domain with its outer side faces laid onto the
+    sphere (curved isoparametric boundary elements) against the same mesh
+    with flat faces: one LSERK stage (stage kernel, plus the curved pass and
+    the save of the curved elements' residual) and dg_run steps."""
+    from workloads import trumpet_domain
+    from workloads.curved import sphere_domain_map, curved_nodes
+    amp, alpha, p0 = 0.1 / 1.4, 2 * np.pi * 565.0 / 343.0, 1.0 / 1.4
+    m = sphere_domain_map(trumpet_domain("sphere", target_K))
+    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, gamma=1.4, rho0=1.0, p0=p0,
+                           inflow_amp=amp, inflow_alpha=alpha)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    K, Np = ctx.K, ctx.Np
+    q = torch.zeros((K, 5, Np), dtype=torch.float32, device=dev)
+    res = torch.zeros_like(q)
+    qb = torch.empty_like(q)
+    dg.dg_autotune(ctx, q, res, None, stream=stream)
+    x = curved_nodes(m, dg.dg_reference_operators(ctx)["rst"])
+    out = {"K": K, "N": N, "steps": steps}
+    for label in ("curved", "flat"):
+        n = dg.dg_set_curved(ctx, x if label == "curved" else None, stream=stream)
+        q.zero_(); res.zero_()
+        t, _ = dg.dg_run(ctx, q, res, 10, 0.5, 0.0, stream=stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        t, dt_last = dg.dg_run(ctx, q, res, steps, 0.5, t, stream=stream)
+        ev[1].record(stream)
+        ev[2].record(stream)
+        for i in range(50):
+            src, dst = (q, qb) if i % 2 == 0 else (qb, q)
+            dg.dg_stage(ctx, src, dst, res, -0.41789047, 0.37921031, t, 1e-5, stream=stream)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / steps
+        out[label] = {"n_curved": n, "ms_per_step": ms, "value": 5 * K * Np * 5 / (ms * 1e-3),
+                      "stage_ms": ev[2].elapsed_time(ev[3]) / 50, "dt_last": dt_last}
+    out["stage_overhead"] = out["curved"]["stage_ms"] / out["flat"]["stage_ms"] - 1.0
+    out["curved_share"] = out["curved"]["n_curved"] / K
+    dg.dg_destroy(ctx)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,9 +369,9 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--form", choices=("fp32", "bf16"), default="fp32",
                     help="form of the headline measurement")
-    ap.add_argument("--also", default="bf16,batch,n5,probes,quadrature",
+    ap.add_argument("--also", default="bf16,batch,n5,probes,quadrature,curved",
                     help="comma list of extra measurements: bf16, fp32, batch, n5, probes, "
-                         "quadrature (or empty)")
+                         "quadrature, curved (or empty)")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--n5-steps", type=int, default=100,
                     help="steps per form of the 1.17M-tet N = 5 precision workload")
@@ -370,6 +413,8 @@ def main():
             extra["probes"] = time_probes(dg, torch, m)
         elif name == "quadrature":
             extra["quadrature"] = time_quadrature(dg, torch, m)
+        elif name == "curved":
+            extra["curved"] = time_curved(dg, torch)
     if args.copy_mb:
         n = args.copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

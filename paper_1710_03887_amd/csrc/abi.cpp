@@ -603,12 +603,16 @@ int dg_set_curved(dg_ctx* c, const double* xyz_nodes, double tol, int64_t* n_cur
   if (n == 0) return DG_OK;
   const int Np = c->ops.Np, NF = 4 * c->ops.Nfp;
   std::vector<float> D(size_t(3) * Np * Np), L(size_t(Np) * NF);
-  for (size_t i = 0; i < size_t(Np) * Np; ++i) {
-    D[i] = float(c->ops.Dr[i]);
-    D[size_t(Np) * Np + i] = float(c->ops.Ds[i]);
-    D[size_t(2) * Np * Np + i] = float(c->ops.Dt[i]);
-  }
-  for (size_t i = 0; i < L.size(); ++i) L[i] = float(c->ops.LIFT[i]);
+  // operators transposed, so that the lanes (one node each) read consecutive words
+  for (int n = 0; n < Np; ++n)
+    for (int j = 0; j < Np; ++j) {
+      const size_t src = size_t(n) * Np + j, dst = size_t(j) * Np + n;
+      D[dst] = float(c->ops.Dr[src]);
+      D[size_t(Np) * Np + dst] = float(c->ops.Ds[src]);
+      D[size_t(2) * Np * Np + dst] = float(c->ops.Dt[src]);
+    }
+  for (int n = 0; n < Np; ++n)
+    for (int i = 0; i < NF; ++i) L[size_t(i) * Np + n] = float(c->ops.LIFT[size_t(n) * NF + i]);
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* p[6] = {};
   const size_t bytes[6] = {size_t(n) * sizeof(int64_t), vg.size() * sizeof(float),

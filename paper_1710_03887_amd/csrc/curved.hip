@@ -49,17 +49,19 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
   constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
   constexpr int Nfp = (N + 1) * (N + 2) / 2;
   constexpr int NF = 4 * Nfp, ST = 5 * Np;
-  constexpr int kSlice = ST + 15 * Np + 10 * NF + NF;
-  __shared__ float lds[kWavesC * kSlice];
+  // per-wavefront slice, 16-byte aligned regions
+  constexpr int oF = (ST + 3) / 4 * 4, oD = oF + 16 * Np, oQ = oD + 8 * NF, oS = oQ + 5 * NF;
+  constexpr int kSlice = (oS + NF + 3) / 4 * 4;
+  __shared__ __align__(16) float lds[kWavesC * kSlice];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t ic = int64_t(blockIdx.x) * kWavesC + w;
   if (ic >= cv.n) return;  // whole wavefront; no block-wide barrier below
   const int64_t k = cv.elem[ic];
   float* sq = lds + w * kSlice;  // [5][Np] state q'
-  float* sF = sq + ST;           // [3 (x,y,z)][5][Np] flux perturbations
-  float* sdF = sF + 15 * Np;     // [NF][5] n.(F- - F+), then the lifted jump
-  float* sdQ = sdF + 5 * NF;     // [NF][5] q- - q+
-  float* sS = sdQ + 5 * NF;      // [NF] max(|u.n| + c) of both sides
+  float* sF = sq + oF;           // [Np][16]: [3 (x,y,z)][5] flux perturbations, padded
+  float* sdF = sq + oD;          // [NF][8]: n.(F- - F+), then the lifted jump (padded)
+  float* sdQ = sq + oQ;          // [NF][5] q- - q+
+  float* sS = sq + oS;           // [NF] max(|u.n| + c) of both sides
   const Phys& P = m.phys;
   const double tst = run ? run->t + c_rk * run->dt : t_host + c_rk * dt_host;
   const float pin = pulse_pressure(P, tst);
@@ -79,7 +81,7 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
       float f[5];
       normal_flux<MOVING>(P, wv, e, f);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sF[(d * 5 + v) * Np + n] = f[v];
+      for (int v = 0; v < 5; ++v) sF[n * 16 + d * 5 + v] = f[v];
     }
   }
   // face jumps at every face node, with that node's own normal
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
     sS[i] = fmaxf(normal_speed<MOVING>(P, wm, nn), normal_speed<MOVING>(P, wp, nn));
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      sdF[i * 5 + v] = fm[v] - fp[v];
+      sdF[i * 8 + v] = fm[v] - fp[v];
       sdQ[i * 5 + v] = qm[v] - qp[v];
     }
   }
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
     for (int j = 0; j < Nfp; ++j) lam = fmaxf(lam, sS[f * Nfp + j]);
     const float fs = cv.sg[(ic * NF + i) * 4 + 3];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) sdF[i * 5 + v] = 0.5f * fs * (sdF[i * 5 + v] - lam * sdQ[i * 5 + v]);
+    for (int v = 0; v < 5; ++v) sdF[i * 8 + v] = 0.5f * fs * (sdF[i * 8 + v] - lam * sdQ[i * 5 + v]);
   }
   wave_sync();
   for (int n = lane; n < Np; n += 64) {
@@ -132,18 +134,26 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
       for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int v = 0; v < 5; ++v) G[a][d][v] = 0.0f;
-    const float* Dn[3] = {cv.D + size_t(n) * Np, cv.D + size_t(Np + n) * Np,
-                          cv.D + size_t(2 * Np + n) * Np};
     for (int j = 0; j < Np; ++j) {
-      const float da[3] = {Dn[0][j], Dn[1][j], Dn[2][j]};
+      // transposed operators: lanes n read consecutive words
+      const float da[3] = {cv.D[size_t(j) * Np + n], cv.D[size_t(Np + j) * Np + n],
+                           cv.D[size_t(2 * Np + j) * Np + n]};
+      // the node's 15 flux values in four 16-byte reads (broadcast to all lanes)
+      float Fj[16];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float4 f4 = reinterpret_cast<const float4*>(sF + j * 16)[c];
+        Fj[4 * c] = f4.x;
+        Fj[4 * c + 1] = f4.y;
+        Fj[4 * c + 2] = f4.z;
+        Fj[4 * c + 3] = f4.w;
+      }
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const float F = sF[(d * 5 + v) * Np + j];
+        for (int v = 0; v < 5; ++v)
 #pragma unroll
-          for (int a = 0; a < 3; ++a) G[a][d][v] += da[a] * F;
-        }
+          for (int a = 0; a < 3; ++a) G[a][d][v] += da[a] * Fj[d * 5 + v];
     }
     const float* g = cv.vg + (ic * Np + n) * 9;
     float gm[9];
@@ -159,11 +169,14 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
         for (int d = 0; d < 3; ++d) div += gm[a * 3 + d] * G[a][d][v];
       r[v] = -div;
     }
-    const float* Ln = cv.L + size_t(n) * NF;
     for (int i = 0; i < NF; ++i) {
-      const float l = Ln[i];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) r[v] += l * sdF[i * 5 + v];
+      const float l = cv.L[size_t(i) * Np + n];
+      const float4 d4 = *reinterpret_cast<const float4*>(sdF + i * 8);
+      r[0] += l * d4.x;
+      r[1] += l * d4.y;
+      r[2] += l * d4.z;
+      r[3] += l * d4.w;
+      r[4] += l * sdF[i * 8 + 4];
     }
     if (m.sigma) {
       const float sgm = m.sigma[k * Np + n];

@@ -16,8 +16,8 @@ struct CurvedSet {
   const int64_t* elem = nullptr; // [n] element ids, ascending
   const float* vg = nullptr;     // [n][Np][9] d r_a / d x_d at each node
   const float* sg = nullptr;     // [n][4][Nfp][4] unit normal, sJ/J at each face node
-  const float* D = nullptr;      // [3][Np][Np] Dr, Ds, Dt (row-major)
-  const float* L = nullptr;      // [Np][4 Nfp] LIFT
+  const float* D = nullptr;      // [3][Np (j)][Np (n)] = D_a[n][j] (Dr, Ds, Dt transposed)
+  const float* L = nullptr;      // [4 Nfp (i)][Np (n)] = LIFT[n][i] (transposed)
   float* res_save = nullptr;     // [n][5][Np] their residual before the stage kernel
 };
 

@@ -591,15 +591,25 @@ __global__ __launch_bounds__(256) void rate_kernel(DeviceMesh m, const float* __
     if (!(w.rho > 0.0f) || !(w.p > 0.0f) || !(rate == rate)) bad = 1u;
     else best = fmaxf(best, rate);
   }
-  // wavefront max, then one atomic per wave (order-independent)
+  // wavefront max, block max, then one atomic per block (order-independent;
+  // one per wave would serialize tens of thousands of atomics on one word)
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     best = fmaxf(best, __shfl_xor(best, off));
     bad |= __shfl_xor(bad, off);
   }
+  __shared__ float wbest[4];
+  __shared__ unsigned wbad[4];
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    atomicMax(&run->rate_bits, __float_as_uint(best));
-    if (bad) atomicOr(&run->bad, 1u);
+    wbest[w] = best;
+    wbad[w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float b = fmaxf(fmaxf(wbest[0], wbest[1]), fmaxf(wbest[2], wbest[3]));
+    atomicMax(&run->rate_bits, __float_as_uint(b));
+    if (wbad[0] | wbad[1] | wbad[2] | wbad[3]) atomicOr(&run->bad, 1u);
   }
 }
 
@@ -725,7 +735,7 @@ template <int N>
 hipError_t rate_dispatch(const DeviceMesh& m, const float* q, RunScalars* run, hipStream_t s) {
   using S = Shape<N>;
   const int64_t total = m.K * S::NF;
-  const int blocks = int(std::min<int64_t>((total + 255) / 256, 4096));
+  const int blocks = int(std::min<int64_t>((total + 255) / 256, 1024));
   rate_kernel<N><<<blocks, 256, 0, s>>>(m, q, run);
   return hipGetLastError();
 }

@@ -16,7 +16,12 @@ signal is recorded every step by the library's probe kernel inside the
 captured step graph, with one fixed time step shared by all domains so that
 the spectra share their frequency bins.
 
-    python -m paper_1710_03887_amd.sensors [--amps 0.005,0.02] [--t-end 3.0]
+    python -m paper_1710_03887_amd.sensors [--amps 0.005,0.02] [--t-end 3.0] [--curved]
+
+With --curved the study compares the spherical domain with flat side faces
+against the same mesh with its side faces laid onto the sphere (curved
+isoparametric elements), adding a sensor pair 5 cm and 4 cm inside the
+curved side wall.
 
 Prints one JSON line per domain run and a summary line: per sensor and
 domain the peak |p'| and the spectrum in dB re 20 micropascal (p0 standing
@@ -72,29 +77,48 @@ def far_wall(m, y=0.0, z=0.003):
     return float(x[hit].max())
 
 
-def sensor_points(m):
+# in the spherical domains, a pair 5 cm and 4 cm inside the sphere's side
+# wall, on the ray from its centre (0.5, 0, 0) at 60 degrees to the axis
+# (closer points fall outside the flat-faced mesh there: its chords lie up to
+# about 3 cm inside the sphere)
+SIDE = ("side 2 (5 cm inside the sphere's side wall)", "side 3 (4 cm inside the sphere's side wall)")
+SIDE_DIR = np.array([0.5, np.sqrt(3.0) / 2.0, 0.0])
+
+
+def sensor_points(m, side=False):
     xf = far_wall(m)
-    return list(SENSORS.values()) + [(xf - 0.02, 0.0, 0.003), (xf - 0.01, 0.0, 0.003)]
+    pts = list(SENSORS.values()) + [(xf - 0.02, 0.0, 0.003), (xf - 0.01, 0.0, 0.003)]
+    if side:
+        c, R = np.array([0.5, 0.0, 0.0]), 1.5
+        pts += [tuple(c + (R - d) * SIDE_DIR + np.array([0.0, 0.0, 0.003])) for d in (0.05, 0.04)]
+    return pts
 
 
-def setup(kind, target_K, amp, N=4):
+def setup(kind, target_K, amp, N=4, side=False):
+    """kind: 'box', 'sphere', 'half', or 'sphere-curved' (the spherical domain
+    with its side faces laid onto the sphere as curved elements)."""
     from workloads import trumpet_domain
     torch = _torch()
-    m = trumpet_domain(kind, target_K)
+    m = trumpet_domain(kind.replace("-curved", ""), target_K)
     ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, gamma=GAMMA, rho0=RHO0, p0=P0,
                            inflow_amp=amp * P0, inflow_alpha=ALPHA)
     q = torch.zeros((ctx.K, 5, ctx.Np), dtype=torch.float32, device="cuda")
     res = torch.zeros_like(q)
+    if kind.endswith("-curved"):
+        from workloads.curved import sphere_domain_map, curved_nodes
+        mc = sphere_domain_map(m)
+        n = dg.dg_set_curved(ctx, curved_nodes(mc, dg.dg_reference_operators(ctx)["rst"]))
+        print(f"{kind}: {n} of {ctx.K} elements curved", flush=True)
     dg.dg_autotune(ctx, q, res)
-    pts = sensor_points(m)
+    pts = sensor_points(m, side)
     dg.dg_probe_setup(ctx, pts)
     return ctx, q, res, pts
 
 
-def record(ctx, q, res, nsteps, dt, chunk=5000, label=""):
+def record(ctx, q, res, nsteps, dt, n_sensors, chunk=5000, label=""):
     """The sensors' p' after every step: device [nsteps, n_sensors]."""
     torch = _torch()
-    series = torch.empty((nsteps, len(SENSORS) + len(FAR)), dtype=torch.float32, device="cuda")
+    series = torch.empty((nsteps, n_sensors), dtype=torch.float32, device="cuda")
     t, done, t0 = 0.0, 0, time.perf_counter()
     while done < nsteps:
         n = min(chunk, nsteps - done)
@@ -118,12 +142,16 @@ def main():
     ap.add_argument("--amps", default="0.005,0.02", help="inflow amplitudes / p0")
     ap.add_argument("--t-end", type=float, default=3.0)
     ap.add_argument("--N", type=int, default=4)
+    ap.add_argument("--curved", action="store_true",
+                    help="compare the spherical domain with flat and with curved side faces")
     args = ap.parse_args()
     torch = _torch()
-    names = list(SENSORS) + list(FAR)
+    names = list(SENSORS) + list(FAR) + (list(SIDE) if args.curved else [])
+    domains = (("sphere", 80_000), ("sphere-curved", 80_000)) if args.curved else DOMAINS
+    ref_kind = domains[0][0]
     summary = {"sensors": SENSORS, "runs": []}
     for amp in [float(a) for a in args.amps.split(",") if a]:
-        ctxs = {kind: setup(kind, K, amp, args.N) for kind, K in DOMAINS}
+        ctxs = {kind: setup(kind, K, amp, args.N, args.curved) for kind, K in domains}
         dt = 0.9 * min(dg.dg_stable_dt(c, q, 0.5) for c, q, _, _ in ctxs.values())
         nsteps = int(math.ceil(args.t_end / dt))
         freqs = np.arange(nsteps // 2 + 1) / (nsteps * dt) * HZ
@@ -131,7 +159,7 @@ def main():
         bins = [int(np.argmin(np.abs(freqs - f))) for f in octaves]
         db, peak = {}, {}
         for kind, (ctx, q, res, pts) in ctxs.items():
-            s, t, secs = record(ctx, q, res, nsteps, dt, label=f"{kind} {amp}")
+            s, t, secs = record(ctx, q, res, nsteps, dt, len(names), label=f"{kind} {amp}")
             db[kind] = spectra(s)
             peak[kind] = s.abs().max(dim=0).values.double().cpu().numpy()
             row = {"amp": amp, "domain": kind, "K": ctx.K, "steps": nsteps, "dt": dt, "t_end": t,
@@ -145,21 +173,26 @@ def main():
             dg.dg_destroy(ctx)
             del q, res
             torch.cuda.empty_cache()
-        ref = db["box"]
+        ref = db[ref_kind]
         for kind in db:
-            if kind == "box":
+            if kind == ref_kind:
                 continue
             diffs = {}
-            for i, nm in enumerate(list(SENSORS)):   # the sensors every domain shares
+            shared = names if args.curved else list(SENSORS)   # the sensors every domain has
+            for i, nm in enumerate(shared):
                 band = (ref[i] > ref[i].max() - 60) & (freqs > 20) & (freqs < 4000)
                 diffs[nm] = float(np.mean(np.abs(db[kind][i, band] - ref[i, band]))) if band.any() else None
-            summary.setdefault("mean_abs_db_vs_box", {}).setdefault(str(amp), {})[kind] = diffs
+            summary.setdefault(f"mean_abs_db_vs_{ref_kind}", {}).setdefault(str(amp), {})[kind] = diffs
         # reflection indicator of the far wall: sensor 3 (1 cm) against sensor 2 (2 cm)
-        i2, i3 = len(SENSORS), len(SENSORS) + 1
-        for kind in db:
-            band = (db[kind][i2] > db[kind][i2].max() - 60) & (freqs > 300) & (freqs < 4000)
-            summary.setdefault("sensor3_minus_sensor2_db", {}).setdefault(str(amp), {})[kind] = \
-                float(np.mean(db[kind][i3, band] - db[kind][i2, band])) if band.any() else None
+        pairs = [("sensor3_minus_sensor2_db", len(SENSORS))]
+        if args.curved:
+            pairs.append(("side3_minus_side2_db", len(SENSORS) + len(FAR)))
+        for key, i2 in pairs:
+            i3 = i2 + 1
+            for kind in db:
+                band = (db[kind][i2] > db[kind][i2].max() - 60) & (freqs > 300) & (freqs < 4000)
+                summary.setdefault(key, {}).setdefault(str(amp), {})[kind] = \
+                    float(np.mean(db[kind][i3, band] - db[kind][i2, band])) if band.any() else None
     print(json.dumps({k: v for k, v in summary.items() if k != "runs"}), flush=True)
 
 

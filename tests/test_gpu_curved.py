@@ -138,3 +138,58 @@ def test_errors():
     with pytest.raises(dg.DGError):
         dg.dg_set_curved(quad, curved_nodes(m, dg.dg_reference_operators(quad)["rst"]))
     dg.dg_destroy(quad)
+
+
+def test_sphere_domain_sampled_parity():
+    """The measured workload: the spherical trumpet domain (about 80,000
+    tets, N = 4) with its outer side faces laid onto the sphere, in the
+    autotuned launch configuration; dg_rhs on sampled curved and straight
+    elements against the oracle on their neighbour patch."""
+    from workloads import trumpet_domain
+    from workloads.curved import sphere_domain_map
+    from helpers import face_keys, neighbour_patch, node_perm, phys_kwargs, ref_of
+    from oracle.mesh import Mesh
+    phys = euler.Physics(amp=0.1 / 1.4, alpha=2 * np.pi * 565.0 / 343.0)
+    m = sphere_domain_map(trumpet_domain("sphere", 80_000))
+    N = 4
+    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, **phys_kwargs(phys))
+    x_lib = curved_nodes(m, dg.dg_reference_operators(ctx)["rst"])
+    n_curved = dg.dg_set_curved(ctx, x_lib)
+    K, Np = ctx.K, ctx.Np
+    assert 0.05 * K < n_curved < 0.5 * K
+    q0 = torch.zeros((K, 5, Np), dtype=torch.float32, device="cuda")
+    dg.dg_autotune(ctx, q0, torch.zeros_like(q0))
+    center, width = (0.5, 1.1, 0.4), 0.4
+    q_lib = euler.initial_state(gaussian_pulse(x_lib, 0.05 * phys.p0, width, center, phys.rho0,
+                                               phys.p0, phys.gamma), phys.gamma)
+    qd = torch.tensor(q_lib - phys.q0[None, :, None], dtype=torch.float32, device="cuda")
+    rd = torch.empty_like(qd)
+    dg.dg_rhs(ctx, qd, rd, 0.02)
+    torch.cuda.synchronize()
+    got_all = rd.double().cpu().numpy()
+    moved = np.abs(x_lib - dg.dg_nodes(ctx)).max(axis=(1, 2)) > 1e-8
+    rng = np.random.Generator(np.random.PCG64(11))
+    # curved elements where the pulse is, plus straight ones
+    xc = x_lib.mean(axis=1)
+    near = np.linalg.norm(xc - np.array(center), axis=1) < 2 * width
+    sample = np.sort(np.concatenate([rng.choice(np.nonzero(moved & near)[0], 48, replace=False),
+                                     rng.choice(np.nonzero(~moved & near)[0], 16, replace=False)]))
+    idx, pm = neighbour_patch(m, sample, face_keys(m["EToV"]))
+    pm["param"], pm["phi"] = m["param"][idx], m["phi"]
+    ref = ref_of(N)
+    mesh = Mesh(ref, pm["xyz"], pm["EToV"], pm["bc"])
+    geo = curved.CurvedGeometry(mesh, curved_nodes(pm, ref.rst))
+    q = euler.initial_state(gaussian_pulse(geo.x, 0.05 * phys.p0, width, center, phys.rho0,
+                                           phys.p0, phys.gamma), phys.gamma)
+    r_or = curved.rhs(mesh, geo, q, 0.02, phys)
+    rows = np.searchsorted(idx, sample)
+    perm = node_perm(ctx, ref)
+    got = np.empty((len(sample), 5, Np))
+    got[:, :, perm] = got_all[sample]
+    err = rel_l2_rows(mesh, rows, got, r_or[rows])
+    c = np.isin(sample, np.nonzero(moved)[0])
+    err_c = rel_l2_rows(mesh, rows[c], got[c], r_or[rows[c]])
+    print(f"sphere domain K={K}, {n_curved} curved: sampled rhs rel L2 {err:.3e} "
+          f"(curved rows {err_c:.3e})")
+    assert err < 2e-5 and err_c < 5e-5
+    dg.dg_destroy(ctx)

@@ -261,3 +261,38 @@ def test_plane_wave_rhs_converges():
         errs_flat.append(e_flat)
     assert errs[2] < errs[1] < errs[0] and errs[2] < 1e-2
     assert errs[2] < errs_flat[2] / 10
+
+
+def test_sphere_domain_map():
+    """The trumpet's spherical domain: side-face nodes land on the sphere,
+    caps stay planar, shared face nodes coincide, Jacobians stay positive,
+    and the curved side boundary's area approaches the closed-form area of
+    the spherical zone between the cap planes, 2 pi R (x_hi - x_lo)."""
+    from workloads import trumpet_domain
+    from workloads.curved import sphere_domain_map
+    m = sphere_domain_map(trumpet_domain("sphere", 6000))
+    c, R = m["sphere"]
+    N = 3
+    mesh = Mesh(ref_of(N), m["xyz"], m["EToV"], m["bc"])
+    geo = curved.CurvedGeometry(mesh, curved_nodes(m, mesh.ref.rst))
+    ref = mesh.ref
+    inner = mesh.mapP >= 0
+    assert np.abs(geo.x[:, ref.Fmask][inner] - geo.x.reshape(-1, 3)[mesh.mapP[inner]]).max() < 1e-13
+    x_lo, x_hi = m["xyz"][..., 0].min(), m["xyz"][..., 0].max()
+    area_c = area_f = 0.0
+    for f in range(4):
+        on = (mesh.EToE[:, f] < 0) & (mesh.bc[:, f] == BC_OUTFLOW_CHAR)
+        xf = geo.x[on][:, ref.Fmask[f]]
+        side = np.ptp(xf[..., 0], axis=1) > 1e-12
+        cap = ~side
+        if side.any():
+            assert np.abs(np.linalg.norm(xf[side] - c, axis=-1) - R).max() < 1e-12
+        if cap.any():
+            assert np.abs(xf[cap][..., 0] - xf[cap][..., :1, 0]).max() < 1e-12   # planar caps
+        w = ref.Emass[f][ref.Fmask[f]].sum(axis=0)
+        k = np.nonzero(on)[0][side]
+        area_c += float(np.sum(geo.Fscale[k, f] * geo.J[k][:, ref.Fmask[f]] * w))
+        area_f += float(np.sum(mesh.Fscale[k, f][:, None] * mesh.J[k][:, None] * w))
+    zone = 2 * np.pi * R * (x_hi - x_lo)
+    print(f"zone area: flat faces {area_f / zone - 1:.2e}, curved {area_c / zone - 1:.2e}")
+    assert abs(area_c / zone - 1) < abs(area_f / zone - 1) / 15
