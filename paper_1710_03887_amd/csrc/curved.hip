@@ -134,6 +134,8 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
       for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int v = 0; v < 5; ++v) G[a][d][v] = 0.0f;
+    // unrolled so that several nodes' operator loads are in flight at once
+#pragma unroll 5
     for (int j = 0; j < Np; ++j) {
       // transposed operators: lanes n read consecutive words
       const float da[3] = {cv.D[size_t(j) * Np + n], cv.D[size_t(Np + j) * Np + n],
@@ -169,6 +171,7 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
         for (int d = 0; d < 3; ++d) div += gm[a * 3 + d] * G[a][d][v];
       r[v] = -div;
     }
+#pragma unroll 6
     for (int i = 0; i < NF; ++i) {
       const float l = cv.L[size_t(i) * Np + n];
       const float4 d4 = *reinterpret_cast<const float4*>(sdF + i * 8);
