@@ -76,7 +76,7 @@ def curved_nodes(m, rst):
     return np.ascontiguousarray(m["phi"](np.einsum("iv,kvd->kid", lam, P)))
 
 
-def sphere_domain_map(m, s0=0.8, tol=1e-9):
+def sphere_domain_map(m, s0=None, tol=1e-9):
     """Map for the trumpet's spherical domain (trumpet_domain('sphere')):
     its outer side vertices lie on the sphere |p - c| = R about the x axis
     and its side faces are flat chords between them; the caps are planes
@@ -87,6 +87,10 @@ def sphere_domain_map(m, s0=0.8, tol=1e-9):
     rho (1 + w (rho_s / rho_f - 1)), w = smoothstep((rho/rho_f - s0)/(1 - s0)),
     which lays the side faces onto the sphere and the caps' rims onto circles
     (the caps stay planar) and leaves every point with rho < s0 rho_f in place.
+    By default s0 = 1 - 0.75 d, d the largest relative radial depth
+    1 - rho/rho_s of a vertex of an element with a face on the curved side:
+    the blend stays inside the layer of boundary elements, so that mostly
+    the elements at the boundary are curved.
     Returns m with 'param' (= xyz) and 'phi' added."""
     xyz, bc = m["xyz"], m["bc"]
     fv = np.array([(0, 1, 2), (0, 1, 3), (1, 2, 3), (0, 2, 3)])
@@ -103,6 +107,12 @@ def sphere_domain_map(m, s0=0.8, tol=1e-9):
     on = np.all(np.abs(np.linalg.norm(tri - np.array([cx, 0, 0]), axis=-1) - R) < 1e-7 * R, axis=1)
     side = tri[on & (np.ptp(tri[..., 0], axis=1) > 0)]           # flat side faces on the sphere
     x_lo, x_hi = side[..., 0].min(axis=1), side[..., 0].max(axis=1)
+    if s0 is None:
+        ks = k[on & (np.ptp(tri[..., 0], axis=1) > 0)]
+        v = xyz[ks].reshape(-1, 3)
+        rs = np.sqrt(np.maximum(R * R - (v[:, 0] - cx) ** 2, 1e-300))
+        depth = float(np.max(1.0 - np.linalg.norm(v[:, 1:], axis=1) / rs))
+        s0 = float(np.clip(1.0 - 0.75 * depth, 0.5, 0.95))
 
     def rho_flat(p):
         """Radius of the flat side boundary on the ray from the axis towards p."""
@@ -152,4 +162,5 @@ def sphere_domain_map(m, s0=0.8, tol=1e-9):
     out["param"] = xyz.copy()
     out["phi"] = phi
     out["sphere"] = (np.array([cx, 0.0, 0.0]), R)
+    out["blend_s0"] = s0
     return out
