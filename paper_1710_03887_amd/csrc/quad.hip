@@ -7,8 +7,11 @@
 // nodal values of the order-N nodes (the same polynomial space and state
 // layout as the nodal scheme); the face rule is symmetric under the face's
 // vertex permutations, so both sides of a face integrate at the same points
-// and the scheme conserves.  One thread per element: its nodal values
-// and right-hand-side accumulators stay in registers; the per-order tables
+// and the scheme conserves.  Four lanes per element: each holds the
+// element's nodal values and its own right-hand-side accumulators in
+// registers, takes every fourth volume point and one face, and the four
+// partial sums are added by lane shuffles (the same order in every lane, so
+// all four hold bit-identical sums); the per-order tables
 // (interpolation to the volume and face points, the weighted derivative
 // and lifting operators, and the neighbour-side interpolation for every
 // face pairing and orientation) are staged in LDS and read at addresses
@@ -106,8 +109,10 @@ __global__ __launch_bounds__(256) void quad_kernel(DeviceMesh m, const float* __
   float rate_best = 0.0f;
   unsigned rate_bad = 0u;
 
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < m.K;
-       k += int64_t(gridDim.x) * blockDim.x) {
+  constexpr int kLanes = 4;          // lanes per element (adjacent lanes)
+  const int g = threadIdx.x & (kLanes - 1);
+  for (int64_t k = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kLanes; k < m.K;
+       k += int64_t(gridDim.x) * blockDim.x / kLanes) {
     float qe[5][Np], acc[5][Np];
     {
       float flat[ST];
@@ -126,7 +131,7 @@ __global__ __launch_bounds__(256) void quad_kernel(DeviceMesh m, const float* __
 
     // volume: sum_q w_q sum_a (d l_i / d r_a) Fc_a, with M^-1 folded in
 #pragma unroll 1
-    for (int q = 0; q < Nq; ++q) {
+    for (int q = g; q < Nq; q += kLanes) {
       float u[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -154,8 +159,8 @@ __global__ __launch_bounds__(256) void quad_kernel(DeviceMesh m, const float* __
     }
 
     // faces: - Fscale_f sum_qf M^-1 l_i w F*.n
-#pragma unroll 1
-    for (int f = 0; f < 4; ++f) {
+    {
+      const int f = g;  // this lane's face
       const int nb = m.nbr[k * 4 + f];
       const float n[3] = {float(m.sgeo[k * 16 + f * 4]), float(m.sgeo[k * 16 + f * 4 + 1]),
                           float(m.sgeo[k * 16 + f * 4 + 2])};
@@ -222,14 +227,23 @@ __global__ __launch_bounds__(256) void quad_kernel(DeviceMesh m, const float* __
       }
     }
 
-    // epilogue
+    // the four lanes' partial sums
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int i = 0; i < Np; ++i) {
+        acc[v][i] += __shfl_xor(acc[v][i], 1);
+        acc[v][i] += __shfl_xor(acc[v][i], 2);
+      }
+
+    // epilogue (stores by the element's first lane)
     if (MODE == MODE_RHS) {
       float flat[ST];
 #pragma unroll
       for (int v = 0; v < 5; ++v)
 #pragma unroll
         for (int i = 0; i < Np; ++i) flat[v * Np + i] = acc[v][i];
-      ElemIO<ST>::store(out + k * ST, flat);
+      if (g == 0) ElemIO<ST>::store(out + k * ST, flat);
     } else {
       float flat[ST];
       if (alpha != 0.0f) {
@@ -246,10 +260,10 @@ __global__ __launch_bounds__(256) void quad_kernel(DeviceMesh m, const float* __
           flat[v * Np + i] = qn_;
           qe[v][i] = qn_;
         }
-      ElemIO<ST>::store(q_out + k * ST, flat);
-      if (rate_out) {  // next step's CFL rate from the new state's face nodes
-#pragma unroll 1
-        for (int f = 0; f < 4; ++f) {
+      if (g == 0) ElemIO<ST>::store(q_out + k * ST, flat);
+      if (rate_out) {  // next step's CFL rate from the new state's nodes on this lane's face
+        {
+          const int f = g;
           const float fs = float(m.sgeo[k * 16 + f * 4 + 3]);
 #pragma unroll 1
           for (int ii = 0; ii < Nfp; ++ii) {
@@ -278,15 +292,23 @@ __global__ __launch_bounds__(256) void quad_kernel(DeviceMesh m, const float* __
       }
     }
   }
-  if (MODE == MODE_STAGE && rate_out) {
+  if (MODE == MODE_STAGE && rate_out) {  // wavefront, then block, then one atomic per block
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       rate_best = fmaxf(rate_best, __shfl_xor(rate_best, off));
       rate_bad |= __shfl_xor(rate_bad, off);
     }
+    __shared__ float wbest[4];
+    __shared__ unsigned wbad[4];
     if ((threadIdx.x & 63) == 0) {
-      atomicMax(&run->rate_bits, __float_as_uint(rate_best));
-      if (rate_bad) atomicOr(&run->bad, 1u);
+      wbest[threadIdx.x >> 6] = rate_best;
+      wbad[threadIdx.x >> 6] = rate_bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const float b = fmaxf(fmaxf(wbest[0], wbest[1]), fmaxf(wbest[2], wbest[3]));
+      atomicMax(&run->rate_bits, __float_as_uint(b));
+      if (wbad[0] | wbad[1] | wbad[2] | wbad[3]) atomicOr(&run->bad, 1u);
     }
   }
 }
@@ -299,8 +321,8 @@ hipError_t launch_nm(const DeviceMesh& m, const float* q_in, const float* q_base
   const void* fn = reinterpret_cast<const void*>(&quad_kernel<N, MODE>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (e != hipSuccess) return e;
-  const int64_t want = (m.K + 255) / 256;
-  const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(m.num_cu) * 4)));
+  const int64_t want = (4 * m.K + 255) / 256;   // four lanes per element
+  const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(m.num_cu) * 16)));
   quad_kernel<N, MODE><<<blocks, 256, lds, s>>>(m, m.qtab, q_in, q_base, q_out, out, alpha, beta,
                                                 c, t_host, dt_host, run, rate_out);
   return hipGetLastError();
