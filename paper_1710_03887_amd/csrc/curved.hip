@@ -5,7 +5,11 @@
 //
 // One wavefront per curved element (four per block); each wavefront stages
 // its element's state, the three Cartesian flux perturbations of every node
-// and the face jumps in its own LDS slice and synchronizes only itself.
+// and the face jumps in its own LDS slice and synchronizes only itself.  The
+// volume contraction G[(a, n)][(d, v)] = sum_j D_a[n][j] F_dv[j] is one dense
+// product, [3 Np x Np] x [Np x 15], on MFMA f32 16x16x4 (the operator packed
+// on the host in the instruction's lane order); each node's lane then applies
+// its nine metric terms.
 // Curved elements are the boundary layer of a curved outer surface, a small
 // share of the mesh: this pass favours plain, exact arithmetic over tiling.
 #include "curved.hpp"
@@ -18,6 +22,8 @@ namespace dg {
 namespace {
 
 constexpr int kWavesC = 4;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -49,25 +55,33 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
   constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
   constexpr int Nfp = (N + 1) * (N + 2) / 2;
   constexpr int NF = 4 * Nfp, ST = 5 * Np;
-  // per-wavefront slice, 16-byte aligned regions
-  constexpr int oF = (ST + 3) / 4 * 4, oD = oF + 16 * Np, oQ = oD + 8 * NF, oS = oQ + 5 * NF;
-  constexpr int kSlice = (oS + NF + 3) / 4 * 4;
+  // MFMA tiling of the volume product: MT row tiles of (a, n), KS steps of 4 nodes
+  constexpr int MT = (3 * Np + 15) / 16, KS = (Np + 3) / 4;
+  // per-wavefront slice, 16-byte aligned regions; the product's rows (sG)
+  // reuse the space of the fluxes and face scratch, dead by then
+  constexpr int oD = (ST + 3) / 4 * 4, oF = oD + 8 * NF, oQ = oF + 16 * 4 * KS, oS = oQ + 5 * NF;
+  constexpr int scratch = (oS + NF - oF) > 16 * 16 * MT ? (oS + NF - oF) : 16 * 16 * MT;
+  constexpr int kSlice = (oF + scratch + 3) / 4 * 4;
   __shared__ __align__(16) float lds[kWavesC * kSlice];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t ic = int64_t(blockIdx.x) * kWavesC + w;
   if (ic >= cv.n) return;  // whole wavefront; no block-wide barrier below
   const int64_t k = cv.elem[ic];
   float* sq = lds + w * kSlice;  // [5][Np] state q'
-  float* sF = sq + oF;           // [Np][16]: [3 (x,y,z)][5] flux perturbations, padded
   float* sdF = sq + oD;          // [NF][8]: n.(F- - F+), then the lifted jump (padded)
+  float* sF = sq + oF;           // [4 KS][16]: [3 (x,y,z)][5] flux perturbations, zero padded
   float* sdQ = sq + oQ;          // [NF][5] q- - q+
   float* sS = sq + oS;           // [NF] max(|u.n| + c) of both sides
+  float* sG = sq + oF;           // [16 MT][16]: the volume product (after the MFMAs)
   const Phys& P = m.phys;
   const double tst = run ? run->t + c_rk * run->dt : t_host + c_rk * dt_host;
   const float pin = pulse_pressure(P, tst);
   const float dt = float(run ? run->dt : dt_host);
 
   for (int i = lane; i < ST; i += 64) sq[i] = q_in[k * ST + i];
+  // zero padding of the flux rows: rows Np .. 4 KS - 1 and column 15
+  for (int i = lane; i < 16 * 4 * KS; i += 64)
+    if (i >= 16 * Np || (i & 15) == 15) sF[i] = 0.0f;
   wave_sync();
   for (int n = lane; n < Np; n += 64) {
     float qq[5];
@@ -126,36 +140,40 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
     for (int v = 0; v < 5; ++v) sdF[i * 8 + v] = 0.5f * fs * (sdF[i * 8 + v] - lam * sdQ[i * 5 + v]);
   }
   wave_sync();
+  // volume product on MFMA: lane l supplies A[row l%16][k l/16] (packed) and
+  // B[k l/16][col l%16] = F of node 4 ks + l/16, column l%16; it holds
+  // D[rows 4 (l/16) .. +3][col l%16] of each row tile
+  {
+    floatx4 acc[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    const float* Ap = cv.D + lane;
+#pragma unroll 3
+    for (int ks = 0; ks < KS; ++ks) {
+      const float b = sF[(4 * ks + (lane >> 4)) * 16 + (lane & 15)];
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ap[(ks * MT + t) * 64], b, acc[t], 0, 0, 0);
+    }
+    wave_sync();  // every lane is done with the fluxes: sG reuses their space
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sG[(16 * t + 4 * (lane >> 4) + i) * 16 + (lane & 15)] = acc[t][i];
+  }
+  wave_sync();
   for (int n = lane; n < Np; n += 64) {
     float G[3][3][5];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) G[a][d][v] = 0.0f;
-    // unrolled so that several nodes' operator loads are in flight at once
-#pragma unroll 5
-    for (int j = 0; j < Np; ++j) {
-      // transposed operators: lanes n read consecutive words
-      const float da[3] = {cv.D[size_t(j) * Np + n], cv.D[size_t(Np + j) * Np + n],
-                           cv.D[size_t(2 * Np + j) * Np + n]};
-      // the node's 15 flux values in four 16-byte reads (broadcast to all lanes)
-      float Fj[16];
+    for (int a = 0; a < 3; ++a) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const float4 f4 = reinterpret_cast<const float4*>(sF + j * 16)[c];
-        Fj[4 * c] = f4.x;
-        Fj[4 * c + 1] = f4.y;
-        Fj[4 * c + 2] = f4.z;
-        Fj[4 * c + 3] = f4.w;
+        const float4 g4 = reinterpret_cast<const float4*>(sG + (a * Np + n) * 16)[c];
+        const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (4 * c + u < 15) G[a][(4 * c + u) / 5][(4 * c + u) % 5] = gv[u];
       }
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int v = 0; v < 5; ++v)
-#pragma unroll
-          for (int a = 0; a < 3; ++a) G[a][d][v] += da[a] * Fj[d * 5 + v];
     }
     const float* g = cv.vg + (ic * Np + n) * 9;
     float gm[9];
