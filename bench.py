@@ -360,6 +360,42 @@ def time_curved(dg, torch, steps=100, target_K=80_000, N=4):
     return out
 
 
+def time_mlp(dg, torch, rows=65_536, batch=4096, steps=40):
+    """The closure's network (78-128-128-75, GELU): Adam steps on 4,096-row
+    minibatches of a 65,536-row synthetic set (the training configuration),
+    and BF16 inference on all rows."""
+    from workloads.mlp_init import init_params
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    m = dg.dg_mlp_create(init_params(0), stream=stream)
+    g = torch.Generator(device="cpu").manual_seed(1)
+    X = torch.randn((rows, dg.MLP_IN), generator=g).to(dev)
+    Y = torch.randn((rows, dg.MLP_OUT), generator=g).to(dev)
+    idx = torch.randint(0, rows, (batch,), generator=g).to(dev)
+    Yo = torch.empty_like(Y)
+    for _ in range(3):
+        dg.dg_mlp_train_step(m, X, Y, 1e-3, rows=idx, want_loss=False, stream=stream)
+        dg.dg_mlp_infer(m, X, Yo, bf16=True, stream=stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    for _ in range(steps):
+        dg.dg_mlp_train_step(m, X, Y, 1e-3, rows=idx, want_loss=False, stream=stream)
+    ev[1].record(stream)
+    ev[2].record(stream)
+    for _ in range(10):
+        dg.dg_mlp_infer(m, X, Yo, bf16=True, stream=stream)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    dg.dg_mlp_destroy(m)
+    step_ms = ev[0].elapsed_time(ev[1]) / steps
+    infer_ms = ev[2].elapsed_time(ev[3]) / 10
+    flop_row = 2 * (78 * 128 + 128 * 128 + 128 * 75)          # forward multiply-adds x 2
+    return {"batch": batch, "train_step_ms": step_ms,
+            "train_TFLOPs": 3 * flop_row * batch / (step_ms * 1e-3) / 1e12,
+            "infer_rows": rows, "infer_ms": infer_ms,
+            "infer_TFLOPs": flop_row * rows / (infer_ms * 1e-3) / 1e12}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,9 +405,9 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--form", choices=("fp32", "bf16"), default="fp32",
                     help="form of the headline measurement")
-    ap.add_argument("--also", default="bf16,batch,n5,probes,quadrature,curved",
+    ap.add_argument("--also", default="bf16,batch,n5,probes,quadrature,curved,mlp",
                     help="comma list of extra measurements: bf16, fp32, batch, n5, probes, "
-                         "quadrature, curved (or empty)")
+                         "quadrature, curved, mlp (or empty)")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--n5-steps", type=int, default=100,
                     help="steps per form of the 1.17M-tet N = 5 precision workload")
@@ -415,6 +451,8 @@ def main():
             extra["quadrature"] = time_quadrature(dg, torch, m)
         elif name == "curved":
             extra["curved"] = time_curved(dg, torch)
+        elif name == "mlp":
+            extra["mlp"] = time_mlp(dg, torch)
     if args.copy_mb:
         n = args.copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
