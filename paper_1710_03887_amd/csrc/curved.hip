@@ -1,7 +1,9 @@
-// Right-hand side of curved (isoparametric) elements: the nodal strong form
-// with the metric terms of each node and the normal and sJ/J of each face
-// node (the volume term in chain-rule form, sum_a sum_d (d r_a/d x_d) D_a F_d,
-// which reduces to the straight-sided operator for constant metric terms).
+// Right-hand side of curved (isoparametric) elements, the remedy Section 3
+// names for the reflections it sees from a spherical boundary built of flat
+// faces: the nodal strong form with the metric terms of each node and the
+// normal and sJ/J of each face node (the volume term in chain-rule form,
+// sum_a sum_d (d r_a/d x_d) D_a F_d, which reduces to the straight-sided
+// operator of Appendix A, Eq. 10, for constant metric terms).
 //
 // One wavefront per curved element (four per block); each wavefront stages
 // its element's state, the three Cartesian flux perturbations of every node

@@ -1,6 +1,7 @@
-// Curved (isoparametric) elements: per-node metric terms and per-face-node
-// normals for the elements whose map is not affine, and the pass that
-// evaluates their right-hand side after the stage kernel.
+// Curved (isoparametric) elements (Section 3: curved boundary faces in place
+// of flat ones): per-node metric terms and per-face-node normals for the
+// elements whose map is not affine, and the pass that evaluates their
+// right-hand side after the stage kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>

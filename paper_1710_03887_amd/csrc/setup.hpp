@@ -71,7 +71,8 @@ struct QuadOps {
 
 std::string build_quadrature(const RefOps& ops, QuadOps& q);
 
-// Curved (isoparametric) elements: each element's map is the degree-N
+// Curved (isoparametric) elements (Section 3 names curved boundary faces as
+// the remedy for reflections from flat ones): each element's map is the degree-N
 // polynomial through the given physical positions of its nodes x [K][Np][3]
 // (node order of ops.rst).  An element is curved when one of its nodes lies
 // farther than tol times its longest edge from the straight-sided position.
