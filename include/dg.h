@@ -418,8 +418,10 @@ int dg_set_damping(dg_ctx* ctx, const float* sigma);
  * Errors: DG_EINVAL for tol <= 0, a context with the quadrature scheme or a
  * learned closure, a node Jacobian <= 0, or node positions that do not
  * coincide (to tol times the edge length) on a shared face; DG_ENODEV on a
- * host-only context; DG_ENOMEM / DG_EHIP.  dg_batch_create and
- * dg_set_learned_bc reject a context with curved elements.  Synchronous. */
+ * host-only context; DG_ENOMEM / DG_EHIP.  Any call first drops the
+ * previous curved set, so after an error the context has none.
+ * dg_batch_create and dg_set_learned_bc reject a context with curved
+ * elements.  Synchronous. */
 int dg_set_curved(dg_ctx* ctx, const double* xyz_nodes, double tol, int64_t* n_curved_out,
                   void* stream);
 
