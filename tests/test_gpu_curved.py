@@ -152,6 +152,14 @@ def test_errors():
     bad[0] = bad[0][::-1]
     with pytest.raises(dg.DGError):
         dg.dg_set_curved(pair.ctx, bad)
+    # after an error the context has no curved set: the straight-sided operator
+    q = euler.initial_state(gaussian_pulse(pair.mesh.x, 0.05 * phys.p0, 0.5, (0.2, 0.1, 0.0),
+                                           phys.rho0, phys.p0, phys.gamma), phys.gamma)
+    qd = pair.to_device(q)
+    rd = torch.empty_like(qd)
+    dg.dg_rhs(pair.ctx, qd, rd, 0.0)
+    torch.cuda.synchronize()
+    assert rel_l2(pair.mesh, pair.rates_from_device(rd), euler.rhs(pair.mesh, q, 0.0, phys)) < 2e-5
     quad = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], 2, quadrature=True)
     with pytest.raises(dg.DGError):
         dg.dg_set_curved(quad, curved_nodes(m, dg.dg_reference_operators(quad)["rst"]))
