@@ -91,11 +91,29 @@ def cpu_baseline(seconds_budget=30.0):
             break
     el = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    return {"value": 5 * mesh.K * ref.Np * stages / el, "unit": "DOF-stage updates/s",
-            "cores": int(threads), "kind": "oracle",
-            "sample": f"trumpet-in-box {mesh.K} tets, N=4, {stages // 5} LSERK step(s) "
-                      f"({stages} RHS evaluations) in {el:.1f} s, FP64 NumPy, "
-                      f"BLAS threads={threads}, host cores={os.cpu_count()}"}
+    # the same right-hand side on one BLAS thread (two evaluations)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        for _ in range(2):
+            euler.rhs(mesh, q, 0.0, phys)
+        el1 = time.perf_counter() - t1
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out = {"value": 5 * mesh.K * ref.Np * stages / el, "unit": "DOF-stage updates/s",
+           "cores": int(threads), "kind": "oracle",
+           "sample": f"trumpet-in-box {mesh.K} tets, N=4, {stages // 5} LSERK step(s) "
+                     f"({stages} RHS evaluations) in {el:.1f} s, FP64 NumPy, "
+                     f"BLAS threads={threads}, host cores={os.cpu_count()}, CPU {model or 'unknown'}"}
+    one = {"value": 5 * mesh.K * ref.Np * 2 / el1, "unit": "DOF-stage updates/s", "threads": 1,
+           "sample": f"2 RHS evaluations of the same sample in {el1:.1f} s"}
+    return out, one
 
 
 def time_single(dg, torch, m, N, form, steps, warmup, kernel_iters):
@@ -491,7 +509,7 @@ def main():
         "forms": extra,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"], out["forms"]["oracle_one_thread"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 
