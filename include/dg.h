@@ -413,12 +413,16 @@ int dg_set_damping(dg_ctx* ctx, const float* sigma);
  * straight elements keep the full-speed path.  Copies what it needs; the
  * host array may be freed on return.  NULL clears the curved set.  Applies
  * to dg_rhs, dg_step, dg_stage, the runs and dg_autotune of this context;
- * probes locate their points with the straight-sided geometry.
+ * dg_probe_setup, called after it, finds a point's reference coordinates in
+ * a curved element by inverting that element's map (Newton's method from
+ * the straight-sided estimate; the element itself is the one the
+ * straight-sided geometry gives).  On a host-only context the curved set is
+ * checked and kept for probe location only.
  * n_curved_out (may be NULL) receives the number of curved elements.
  * Errors: DG_EINVAL for tol <= 0, a context with the quadrature scheme or a
  * learned closure, a node Jacobian <= 0, or node positions that do not
- * coincide (to tol times the edge length) on a shared face; DG_ENODEV on a
- * host-only context; DG_ENOMEM / DG_EHIP.  Any call first drops the
+ * coincide (to tol times the edge length) on a shared face; DG_ENOMEM /
+ * DG_EHIP.  Any call first drops the
  * previous curved set, so after an error the context has none.
  * dg_batch_create and dg_set_learned_bc reject a context with curved
  * elements.  Synchronous. */
@@ -442,8 +446,11 @@ int dg_set_curved(dg_ctx* ctx, const double* xyz_nodes, double tol, int64_t* n_c
  * its interpolation weights w (value at the point = sum_i w[i] u[node i], in
  * the library's node order); either may be NULL.  On a host-only context
  * the points are located and weighed but no probe set is kept.
- * Synchronous.  Errors: DG_EINVAL for n outside 1..2^20 or a point outside
- * the mesh (tolerance 1e-9 in barycentric coordinates), DG_ENOMEM. */
+ * In an element of the curved set (dg_set_curved, set before) the point's
+ * reference coordinates come from inverting that element's curved map.
+ * Synchronous.  Errors: DG_EINVAL for n outside 1..2^20, a point outside
+ * the mesh (tolerance 1e-9 in barycentric coordinates) or a curved map that
+ * does not invert, DG_ENOMEM. */
 int dg_probe_setup(dg_ctx* ctx, const double* xyz, int32_t n, int64_t* elements_out,
                    double* weights_out);
 

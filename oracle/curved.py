@@ -27,6 +27,7 @@ isoparametric treatment of the nodal scheme:
 import numpy as np
 
 from .euler import flux, ghost_state, normal_flux, primitive, sound_speed
+from .operators import vandermonde
 
 # outward reference normal of each face as a combination of grad r, grad s, grad t
 FACE_GRAD = np.array([[0.0, 0.0, -1.0], [0.0, -1.0, 0.0], [1.0, 1.0, 1.0], [-1.0, 0.0, 0.0]])
@@ -82,3 +83,32 @@ def rhs(mesh, geo, q, t, phys, sigma=None):
     if sigma is not None:
         out -= sigma[:, None, :] * (q - phys.q0[None, :, None])
     return out
+
+
+def locate(mesh, geo, points, curved_rows):
+    """Element [n] and reference coordinates [n, 3] of each point: the
+    element the straight-sided geometry gives (oracle.probes.locate); in an
+    element of `curved_rows` (a boolean [K] mask) the reference point solves
+    x(r) = point for that element's curved map, by Newton's method from the
+    straight-sided estimate with the map's exact derivative."""
+    from .probes import locate as locate_straight
+    ref = mesh.ref
+    elem, rst = locate_straight(mesh, points)
+    Vinv = np.linalg.inv(ref.V)
+    pts = np.atleast_2d(np.asarray(points, dtype=np.float64))
+    for p, k in enumerate(elem):
+        if k < 0 or not curved_rows[k]:
+            continue
+        xe, r = geo.x[k], rst[p].copy()
+        for _ in range(50):
+            V, Vr, Vs, Vt = vandermonde(ref.N, r[None])
+            f = (V @ Vinv @ xe)[0] - pts[p]
+            Jm = np.stack([(D @ Vinv @ xe)[0] for D in (Vr, Vs, Vt)], axis=1)
+            dr = np.linalg.solve(Jm, f)
+            r -= dr
+            if np.abs(dr).max() <= 1e-13:
+                break
+        else:
+            raise ValueError(f"point {p}: the curved map of element {k} did not invert")
+        rst[p] = r
+    return elem, rst

@@ -58,6 +58,8 @@ void free_curved(dg_ctx* c) {
   for (void* p : c->curved_allocs) (void)hipFree(p);
   c->curved_allocs.clear();
   c->curved = dg::CurvedSet{};
+  c->curved_elem_host.clear();
+  c->curved_x_host.clear();
 }
 
 void free_device(dg_ctx* c) {
@@ -586,10 +588,9 @@ int dg_set_damping(dg_ctx* c, const float* sigma) {
 
 int dg_set_curved(dg_ctx* c, const double* xyz_nodes, double tol, int64_t* n_curved_out,
                   void* stream) {
-  int rc = need_device(c);
-  if (rc) return rc;
+  if (!c) return fail(nullptr, DG_EINVAL, "null context");
   if (n_curved_out) *n_curved_out = 0;
-  drop_graphs(c);
+  if (!c->host_only) drop_graphs(c);
   free_curved(c);
   if (!xyz_nodes) return DG_OK;
   if (!(tol > 0.0)) return fail(c, DG_EINVAL, "tol must be positive");
@@ -602,6 +603,16 @@ int dg_set_curved(dg_ctx* c, const double* xyz_nodes, double tol, int64_t* n_cur
   const int64_t n = int64_t(elems.size());
   if (n == 0) return DG_OK;
   const int Np = c->ops.Np, NF = 4 * c->ops.Nfp;
+  // host copies for locating probes in curved elements
+  c->curved_elem_host = elems;
+  c->curved_x_host.resize(size_t(n) * Np * 3);
+  for (int64_t i = 0; i < n; ++i)
+    std::copy(xyz_nodes + size_t(elems[i]) * Np * 3, xyz_nodes + size_t(elems[i] + 1) * Np * 3,
+              c->curved_x_host.begin() + size_t(i) * Np * 3);
+  if (c->host_only) {  // checked and kept for probe location only
+    if (n_curved_out) *n_curved_out = n;
+    return DG_OK;
+  }
   // Dr, Ds, Dt packed as the MFMA A operand (lane order, zero padded); LIFT
   // transposed, so that the lanes (one node each) read consecutive words
   const int MT = (3 * Np + 15) / 16, KS = (Np + 3) / 4;
@@ -661,6 +672,13 @@ int dg_probe_setup(dg_ctx* c, const double* xyz, int32_t n, int64_t* elements_ou
     double rst[3];
     elem[p] = dg::locate_point(c->mesh, xyz + size_t(p) * 3, 1e-9, rst);
     if (elem[p] < 0) return fail(c, DG_EINVAL, "probe " + std::to_string(p) + " lies outside the mesh");
+    // in a curved element: invert its curved map, from the straight-sided estimate
+    const auto it = std::lower_bound(c->curved_elem_host.begin(), c->curved_elem_host.end(), elem[p]);
+    if (it != c->curved_elem_host.end() && *it == elem[p]) {
+      const size_t ci = size_t(it - c->curved_elem_host.begin());
+      if (!dg::invert_element_map(c->ops, c->curved_x_host.data() + ci * Np * 3, xyz + size_t(p) * 3, rst))
+        return fail(c, DG_EINVAL, "probe " + std::to_string(p) + ": its curved element's map did not invert");
+    }
     dg::interpolation_weights(c->ops, rst, wd.data());
     for (int i = 0; i < Np; ++i) w[size_t(p) * Np + i] = float(wd[i]);
     if (weights_out) std::copy(wd.begin(), wd.end(), weights_out + size_t(p) * Np);

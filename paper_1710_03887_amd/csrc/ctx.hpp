@@ -68,6 +68,8 @@ struct dg_ctx {
   int64_t last_bad = -1;
   dg::CurvedSet curved;             // curved elements (n = 0: none)
   std::vector<void*> curved_allocs;
+  std::vector<int64_t> curved_elem_host;  // the curved elements, ascending
+  std::vector<double> curved_x_host;      // their node positions [n][Np][3]
 };
 
 // Captured step graphs are rebuilt after anything they bake in changes

@@ -696,6 +696,51 @@ void interpolation_weights(const RefOps& ops, const double rst[3], double* w) {
   }
 }
 
+bool invert_element_map(const RefOps& ops, const double* xe, const double x[3], double rst[3]) {
+  const int N = ops.N, Np = ops.Np;
+  std::vector<double> psi(size_t(4) * Np), w(size_t(4) * Np);
+  for (int it = 0; it < 50; ++it) {
+    int m = 0;
+    for (int i = 0; i <= N; ++i)
+      for (int j = 0; j <= N - i; ++j)
+        for (int k = 0; k <= N - i - j; ++k, ++m)
+          basis3(i, j, k, rst[0], rst[1], rst[2], psi[m], psi[Np + m], psi[2 * Np + m],
+                 psi[3 * Np + m]);
+    // weights of the value and of its r, s, t derivatives at rst
+    for (int c = 0; c < 4; ++c)
+      for (int n = 0; n < Np; ++n) {
+        double acc = 0.0;
+        for (int mm = 0; mm < Np; ++mm) acc += psi[size_t(c) * Np + mm] * ops.Vinv[size_t(mm) * Np + n];
+        w[size_t(c) * Np + n] = acc;
+      }
+    double f[3] = {-x[0], -x[1], -x[2]}, J[3][3] = {};
+    for (int n = 0; n < Np; ++n)
+      for (int d = 0; d < 3; ++d) {
+        f[d] += w[n] * xe[n * 3 + d];
+        for (int a = 0; a < 3; ++a) J[d][a] += w[size_t(a + 1) * Np + n] * xe[n * 3 + d];
+      }
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    if (!(std::fabs(det) > 0.0)) return false;
+    // dr = J^-1 f by cofactors
+    const double inv[3][3] = {
+        {c00 / det, (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det, (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det},
+        {c01 / det, (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det, (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det},
+        {c02 / det, (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det, (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det}};
+    double step = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double dr = inv[a][0] * f[0] + inv[a][1] * f[1] + inv[a][2] * f[2];
+      rst[a] -= dr;
+      step = std::max(step, std::fabs(dr));
+    }
+    if (!std::isfinite(step)) return false;
+    if (step <= 1e-13) return true;
+  }
+  return false;
+}
+
 namespace {
 
 // Gauss-Jacobi rule with n points for the weight (1-x)^al on [-1,1]: the

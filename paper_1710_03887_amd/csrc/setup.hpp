@@ -93,6 +93,12 @@ std::string curved_geometry(const RefOps& ops, const HostMesh& mesh, const doubl
 // rst receives the point's reference coordinates in that element.
 int64_t locate_point(const HostMesh& mesh, const double x[3], double tol, double rst[3]);
 
+// Reference coordinates of the physical point x in an element whose map is
+// the degree-N polynomial through its node positions xe [Np][3]: Newton's
+// method on x(r) = sum_i l_i(r) xe_i from the starting point rst (updated in
+// place).  Returns false when it does not converge (|step| <= 1e-13 within
+// 50 iterations) or meets a singular Jacobian.
+bool invert_element_map(const RefOps& ops, const double* xe, const double x[3], double rst[3]);
 // Nodal interpolation weights w[i] = l_i(r, s, t) of the order-N nodal basis
 // at a reference point: the polynomial through nodal values u_i takes the
 // value sum_i w[i] u_i there.

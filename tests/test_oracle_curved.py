@@ -296,3 +296,55 @@ def test_sphere_domain_map():
     zone = 2 * np.pi * R * (x_hi - x_lo)
     print(f"zone area: flat faces {area_f / zone - 1:.2e}, curved {area_c / zone - 1:.2e}")
     assert abs(area_c / zone - 1) < abs(area_f / zone - 1) / 15
+
+
+def _curved_points(mesh, geo, rows, rng):
+    """Images under the curved maps of random reference points well inside
+    the elements `rows` (barycentric coordinates >= 0.15)."""
+    ref = mesh.ref
+    lam = rng.dirichlet(np.ones(4), size=len(rows)) * 0.4 + 0.15
+    r0 = 2.0 * lam[:, 1:] - 1.0
+    Vinv = np.linalg.inv(ref.V)
+    pts = np.stack([(vandermonde(ref.N, r0[i][None])[0] @ Vinv @ geo.x[k])[0] for i, k in enumerate(rows)])
+    return pts, r0
+
+
+def test_locate_in_curved_elements():
+    """Newton's inversion of a curved map recovers the reference point that
+    the forward map sent to x, in the element the straight geometry names."""
+    m, mesh, geo = capped(3, n=3)
+    moved = np.abs(geo.x - mesh.x).max(axis=(1, 2)) > 1e-8
+    rng = np.random.default_rng(5)
+    rows = rng.choice(np.nonzero(moved)[0], 30, replace=False)
+    pts, r0 = _curved_points(mesh, geo, rows, rng)
+    elem, rst = curved.locate(mesh, geo, pts, moved)
+    same = elem == rows
+    assert same.sum() >= 25                     # a point near a face may fall to the neighbour
+    assert np.abs(rst[same] - r0[same]).max() < 1e-10
+
+
+def test_library_curved_probe_weights_match_oracle():
+    """The library's host path (host-only context, no GPU): dg_set_curved
+    keeps the curved set, dg_probe_setup inverts curved maps; same elements
+    and weights node by node as the oracle."""
+    import paper_1710_03887_amd as dg
+    from helpers import node_perm
+    from oracle import probes
+    m, mesh, geo = capped(3, n=3)
+    moved = np.abs(geo.x - mesh.x).max(axis=(1, 2)) > 1e-8
+    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], 3, host_only=True)
+    n = dg.dg_set_curved(ctx, curved_nodes(m, dg.dg_reference_operators(ctx)["rst"]))
+    assert n == moved.sum()
+    rng = np.random.default_rng(6)
+    rows = np.concatenate([rng.choice(np.nonzero(moved)[0], 20, replace=False),
+                           rng.choice(np.nonzero(~moved)[0], 10, replace=False)])
+    pts, _ = _curved_points(mesh, geo, rows, rng)
+    e_or, rst = curved.locate(mesh, geo, pts, moved)
+    e_lib, w_lib = dg.dg_probe_setup(ctx, pts, weights=True)
+    assert np.array_equal(e_lib, e_or)
+    w_or = probes.weights(mesh.ref, rst)
+    assert np.abs(w_lib - w_or[:, node_perm(ctx, mesh.ref)]).max() < 1e-10
+    # without the curved set the straight-sided weights differ in curved elements
+    dg.dg_set_curved(ctx, None)
+    _, w_flat = dg.dg_probe_setup(ctx, pts, weights=True)
+    assert np.abs(w_flat - w_lib)[np.isin(e_lib, np.nonzero(moved)[0])].max() > 1e-4
