@@ -219,3 +219,31 @@ def test_sphere_domain_sampled_parity():
           f"(curved rows {err_c:.3e})")
     assert err < 2e-5 and err_c < 5e-5
     dg.dg_destroy(ctx)
+
+
+def test_probe_sample_in_curved_elements():
+    """p' sampled by the probe kernel at points inside curved elements (the
+    curved map inverted at setup) against the oracle's interpolation of the
+    same state at the same reference points."""
+    from oracle import probes
+    phys = euler.Physics()
+    m, pair, geo, _ = _setup(3, phys)
+    moved = np.abs(geo.x - pair.mesh.x).max(axis=(1, 2)) > 1e-8
+    rng = np.random.default_rng(7)
+    rows = rng.choice(np.nonzero(moved)[0], 12, replace=False)
+    ref = pair.ref
+    lam = rng.dirichlet(np.ones(4), size=len(rows)) * 0.4 + 0.15
+    r0 = 2.0 * lam[:, 1:] - 1.0
+    pts = np.stack([(probes.weights(ref, r0[i][None]) @ geo.x[k])[0] for i, k in enumerate(rows)])
+    q = euler.initial_state(gaussian_pulse(geo.x, 0.05 * phys.p0, 0.5, (0.6, 0.1, 0.0), phys.rho0,
+                                           phys.p0, phys.gamma), phys.gamma)
+    e_or, rst = curved.locate(pair.mesh, geo, pts, moved)
+    p_or = probes.sample(pair.mesh, q, e_or, probes.weights(ref, rst), phys)
+    dg.dg_probe_setup(pair.ctx, pts)
+    out = torch.empty(len(pts), dtype=torch.float32, device="cuda")
+    dg.dg_probe_sample(pair.ctx, pair.to_device(q), out)
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    err = np.abs(got - p_or).max() / np.abs(p_or).max()
+    print(f"curved probes: max rel difference {err:.2e}")
+    assert err < 1e-5
