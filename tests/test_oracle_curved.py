@@ -348,3 +348,36 @@ def test_library_curved_probe_weights_match_oracle():
     dg.dg_set_curved(ctx, None)
     _, w_flat = dg.dg_probe_setup(ctx, pts, weights=True)
     assert np.abs(w_flat - w_lib)[np.isin(e_lib, np.nonzero(moved)[0])].max() > 1e-4
+
+
+def test_library_curved_set_rejections_host_only():
+    """dg_set_curved's checks on the host (no GPU): tol <= 0, node positions
+    that differ on the two sides of a shared face, a node Jacobian <= 0, and
+    a quadrature-scheme context; a rejected call leaves no curved set."""
+    import paper_1710_03887_amd as dg
+    m, mesh, geo = capped(2, n=2)
+    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], 2, host_only=True)
+    ops = dg.dg_reference_operators(ctx)
+    x = curved_nodes(m, ops["rst"])
+    assert dg.dg_set_curved(ctx, x) > 0
+    with pytest.raises(dg.DGError):
+        dg.dg_set_curved(ctx, x, tol=0.0)
+    mapP = dg.dg_geometry(ctx)["mapP"]
+    k, f = [(k, f) for k in range(ctx.K) for f in range(4) if mapP[k, f, 0] >= 0][0]
+    bad = x.copy()
+    bad[k, ops["Fmask"][f, -1]] += 1e-3
+    with pytest.raises(dg.DGError, match="coincide"):
+        dg.dg_set_curved(ctx, bad)
+    bad = x.copy()
+    bad[0] = bad[0][::-1]
+    with pytest.raises(dg.DGError):
+        dg.dg_set_curved(ctx, bad)
+    # nothing kept after the rejection: probes use the straight-sided weights
+    pts = mesh.x[:3].mean(axis=1)
+    e, w = dg.dg_probe_setup(ctx, pts, weights=True)
+    dg.dg_set_curved(ctx, None)
+    e2, w2 = dg.dg_probe_setup(ctx, pts, weights=True)
+    assert np.array_equal(e, e2) and np.abs(w - w2).max() == 0.0
+    quad = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], 2, host_only=True, quadrature=True)
+    with pytest.raises(dg.DGError):
+        dg.dg_set_curved(quad, x)
