@@ -200,29 +200,69 @@ __global__ __launch_bounds__(256) void quad_kernel(DeviceMesh m, const float* __
         if (nb < 0) ghost(P, tag, qm, wm, n, pin, qp);
         primitive<true>(P, qp, wp);
       };
-      float lam = 0.0f;
+      if constexpr (N == 1) {
+        // one pass over the face's points: lambda is one per face, so its
+        // term lambda (q- - q+)/2 is lifted separately and scaled at the end
+        float lam = 0.0f;
+        float dql[5][Np];
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+#pragma unroll
+          for (int i = 0; i < Np; ++i) dql[v][i] = 0.0f;
 #pragma unroll 1
-      for (int qf = 0; qf < Nfq; ++qf) {
-        float qm[5], qp[5];
-        Prim wm, wp;
-        sides(qf, qm, wm, qp, wp);
-        lam = fmaxf(lam, fmaxf(normal_speed<true>(P, wm, n), normal_speed<true>(P, wp, n)));
-      }
+        for (int qf = 0; qf < Nfq; ++qf) {
+          float qm[5], qp[5], fm[5], fp[5];
+          Prim wm, wp;
+          sides(qf, qm, wm, qp, wp);
+          lam = fmaxf(lam, fmaxf(normal_speed<true>(P, wm, n), normal_speed<true>(P, wp, n)));
+          normal_flux<true>(P, wm, n, fm);
+          normal_flux<true>(P, wp, n, fp);
+          float Fa[5], dq[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            Fa[v] = 0.5f * fs * (fm[v] + fp[v]);
+            dq[v] = qm[v] - qp[v];
+          }
+#pragma unroll
+          for (int i = 0; i < Np; ++i) {
+            const float l = T[S::oLq + (f * Np + i) * Nfq + qf];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+              acc[v][i] -= l * Fa[v];
+              dql[v][i] += l * dq[v];
+            }
+          }
+        }
+        const float cl = 0.5f * fs * lam;
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+#pragma unroll
+          for (int i = 0; i < Np; ++i) acc[v][i] -= cl * dql[v][i];
+      } else {  // at N = 2 the extra accumulators would cost occupancy: two passes
+        float lam = 0.0f;
 #pragma unroll 1
-      for (int qf = 0; qf < Nfq; ++qf) {
-        float qm[5], qp[5], fm[5], fp[5];
-        Prim wm, wp;
-        sides(qf, qm, wm, qp, wp);
-        normal_flux<true>(P, wm, n, fm);
-        normal_flux<true>(P, wp, n, fp);
-        float Fn[5];
+        for (int qf = 0; qf < Nfq; ++qf) {
+          float qm[5], qp[5];
+          Prim wm, wp;
+          sides(qf, qm, wm, qp, wp);
+          lam = fmaxf(lam, fmaxf(normal_speed<true>(P, wm, n), normal_speed<true>(P, wp, n)));
+        }
+#pragma unroll 1
+        for (int qf = 0; qf < Nfq; ++qf) {
+          float qm[5], qp[5], fm[5], fp[5];
+          Prim wm, wp;
+          sides(qf, qm, wm, qp, wp);
+          normal_flux<true>(P, wm, n, fm);
+          normal_flux<true>(P, wp, n, fp);
+          float Fn[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Fn[v] = fs * (0.5f * (fm[v] + fp[v]) + 0.5f * lam * (qm[v] - qp[v]));
+          for (int v = 0; v < 5; ++v) Fn[v] = fs * (0.5f * (fm[v] + fp[v]) + 0.5f * lam * (qm[v] - qp[v]));
 #pragma unroll
-        for (int i = 0; i < Np; ++i) {
-          const float l = T[S::oLq + (f * Np + i) * Nfq + qf];
+          for (int i = 0; i < Np; ++i) {
+            const float l = T[S::oLq + (f * Np + i) * Nfq + qf];
 #pragma unroll
-          for (int v = 0; v < 5; ++v) acc[v][i] -= l * Fn[v];
+            for (int v = 0; v < 5; ++v) acc[v][i] -= l * Fn[v];
+          }
         }
       }
     }
