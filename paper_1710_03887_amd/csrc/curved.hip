@@ -11,9 +11,10 @@
 // volume contraction G[(a, n)][(d, v)] = sum_j D_a[n][j] F_dv[j] is one dense
 // product, [3 Np x Np] x [Np x 15], on MFMA f32 16x16x4 (the operator packed
 // on the host in the instruction's lane order); each node's lane then applies
-// its nine metric terms.
-// Curved elements are the boundary layer of a curved outer surface, a small
-// share of the mesh: this pass favours plain, exact arithmetic over tiling.
+// its nine metric terms.  Curved elements are the boundary layer of a curved
+// outer surface, a small share of the mesh, so one element per wavefront
+// (rather than the stage kernel's tiles) keeps this pass simple; its time is
+// the latency of each element's chain of phases.
 #include "curved.hpp"
 
 #include <algorithm>
