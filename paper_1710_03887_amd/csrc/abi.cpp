@@ -637,6 +637,7 @@ int dg_set_curved(dg_ctx* c, const double* xyz_nodes, double tol, int64_t* n_cur
     const hipError_t e = hipMalloc(&p[i], bytes[i]);
     if (e != hipSuccess) {
       for (int j = 0; j < i; ++j) (void)hipFree(p[j]);
+      free_curved(c);  // no half-set curved state (host copies included)
       return fail(c, DG_ENOMEM, "hipMalloc for curved elements");
     }
   }
