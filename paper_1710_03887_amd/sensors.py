@@ -8,8 +8,9 @@ the same pulse in each, and compares the pressure spectra at sensors near the
 bell and near the outer boundary (Table 2 gives each sensor's distance from
 the bell and from the boundary): matching spectra mean the boundary
 treatment let the pulse out without disturbing the solution.  Here the
-domains are the synthetic trumpet domains of this package (box, sphere of
-radius 1.5, half domain), the sensors stand-ins placed by their relation to
+domains are the synthetic trumpet domains of this package (Type A: box,
+sphere of radius 1.5, cone; Type B: half box, half cone), the sensors
+stand-ins placed by their relation to
 the bell plane (x = 1): three at the same place in every domain, and on the
 axis a pair 2 cm and 1 cm before each domain's own far wall, and every
 signal is recorded every step by the library's probe kernel inside the
@@ -50,7 +51,8 @@ SENSORS = {
 }
 # ... and, per domain, on the axis 2 cm and 1 cm before its own far wall
 FAR = ("sensor 2 (on axis, 2 cm before the far wall)", "sensor 3 (on axis, 1 cm before the far wall)")
-DOMAINS = (("box", 50_000), ("sphere", 80_000), ("half", 30_000))
+DOMAINS = (("box", 50_000), ("sphere", 80_000), ("cone", 80_000), ("half", 30_000),
+           ("half-cone", 40_000))
 
 
 def _torch():

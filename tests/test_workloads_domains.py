@@ -1,0 +1,36 @@
+"""The synthetic outer domains of the sensor study (box, sphere, cone, half
+box, half cone): valid conforming meshes, the circular domains' side
+vertices on their sphere / cone, and every sensor inside every domain."""
+import numpy as np
+import pytest
+
+from oracle.mesh import Mesh
+from oracle.operators import RefElement
+from oracle import probes
+from workloads import trumpet_domain, BC_OUTFLOW_CHAR
+from workloads.trumpet import CONE_APEX_X, CONE_SLOPE
+from paper_1710_03887_amd.sensors import SENSORS, sensor_points
+
+
+@pytest.mark.parametrize("kind", ["box", "sphere", "cone", "half", "half-cone"])
+def test_domain_mesh_and_sensors(kind):
+    m = trumpet_domain(kind, 6000)
+    mesh = Mesh(RefElement(1), m["xyz"], m["EToV"], m["bc"])
+    k, f = np.nonzero((mesh.EToE < 0) & (mesh.bc == BC_OUTFLOW_CHAR))
+    assert len(k) > 0
+    if kind.endswith("cone") or kind == "sphere":
+        fv = np.array([(0, 1, 2), (0, 1, 3), (1, 2, 3), (0, 2, 3)])
+        tri = mesh.xyz[k[:, None], fv[f]]
+        side = np.ptp(tri[..., 0], axis=1) > 1e-12                 # faces spanning two planes
+        v = tri[side].reshape(-1, 3)
+        rho = np.linalg.norm(v[:, 1:], axis=1)
+        if kind == "sphere":
+            on = np.abs(np.linalg.norm(v - np.array([0.5, 0, 0]), axis=1) - 1.5) < 1e-9
+        else:
+            on = np.abs(rho - CONE_SLOPE * (v[:, 0] - CONE_APEX_X)) < 1e-9
+        # the outer side faces: all their vertices on the surface (the
+        # half domains' x = 1 plane also carries outflow faces)
+        tri_on = on.reshape(-1, 3).all(axis=1)
+        assert tri_on.sum() > 0.5 * side.sum()
+    elem, _ = probes.locate(mesh, sensor_points(m))
+    assert (elem >= 0).all(), (kind, elem)

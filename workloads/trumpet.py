@@ -20,8 +20,11 @@ depends only on the shared edge, so the tetrahedral mesh is conforming.
 
 Outer domains: 'box' [-0.5, 1.8] x [-1, 1]^2; 'sphere' of radius 1.5 about
 (0.5, 0, 0), cut by the planes where its cross-section becomes narrower than
-the grid needs (flat caps); 'half': the bore plus the box region x >= 1 in
-front of the bell (the region behind the bell is left out).  `scale` grows
+the grid needs (flat caps); 'cone': x in [-0.5, 1.8] inside the cone of
+half-angle 30 degrees about the x axis with its apex at x = -1.3 (radius 0.46
+at the back cap, 1.79 at the front cap); 'half': the bore plus the box region
+x >= 1 in front of the bell (the region behind the bell is left out);
+'half-cone': the bore plus the cone region x >= 1.  `scale` grows
 the outer domain linearly about (0.65, 0, 0) with the instrument fixed.
 """
 import numpy as np
@@ -33,6 +36,7 @@ BELL_X0, BELL_X1 = 0.7, 1.0
 MOUTH_R = 0.4
 KAPPA = np.log(MOUTH_R / BORE_R) / (BELL_X1 - BELL_X0)
 CENTER_X = 0.65
+CONE_APEX_X, CONE_SLOPE = -1.3, float(np.tan(np.pi / 6))
 
 
 def instrument_radius(x):
@@ -135,8 +139,9 @@ def trumpet_domain(kind="box", target_K=200_000, scale=1.0, wall_tag=BC_WALL,
     Returns {'xyz', 'EToV', 'bc'} (see meshes.py) and, with return_info,
     an 'info' dict with the grid sizes and the wall/inflow geometry.
     """
-    if kind not in ("box", "sphere", "half"):
-        raise ValueError("kind must be 'box', 'sphere' or 'half'")
+    if kind not in ("box", "sphere", "half", "cone", "half-cone"):
+        raise ValueError("kind must be 'box', 'sphere', 'half', 'cone' or 'half-cone'")
+    halfk = kind in ("half", "half-cone")
     if kind == "sphere":
         x_lo, x_hi, half_w = 0.5 - 1.5, 0.5 + 1.5, 1.5
     else:
@@ -145,6 +150,7 @@ def trumpet_domain(kind="box", target_K=200_000, scale=1.0, wall_tag=BC_WALL,
     x_hi = CENTER_X + (x_hi - CENTER_X) * scale
     half_w *= scale
     sph_c, sph_r = np.array([0.5, 0.0, 0.0]), 1.5 * scale
+    cone = (CENTER_X + (CONE_APEX_X - CENTER_X) * scale, CONE_SLOPE) if kind.endswith("cone") else None
 
     def layout(s):
         nt = max(2, int(round(6 * s)))
@@ -167,7 +173,7 @@ def trumpet_domain(kind="box", target_K=200_000, scale=1.0, wall_tag=BC_WALL,
         nt, nr1, nr2, xs = layout(s)
         nq = nt * nt + 4 * nt * (nr1 + nr2)
         K = 6 * nq * (len(xs) - 1)
-        if kind == "half":
+        if halfk:
             # rough: bore interior for x < 1 plus everything in front
             front = np.sum(xs >= BELL_X1) - 1
             inner = nt * nt + 4 * nt * nr1
@@ -181,16 +187,18 @@ def trumpet_domain(kind="box", target_K=200_000, scale=1.0, wall_tag=BC_WALL,
             break
         s *= (target_K / K) ** (1.0 / 3.0)
     nt, nr1, nr2, xs = layout(s)
-    if kind == "half":
+    if halfk:
         xs = xs[xs >= 0.0]
     return _assemble(kind, nt, nr1, nr2, xs, x_lo, x_hi, half_w, sph_c, sph_r, wall_tag,
-                     inflow_tag, outer_tag, return_info, scale)
+                     inflow_tag, outer_tag, return_info, scale, cone=cone)
 
 
 def _assemble(kind, nt, nr1, nr2, xs, x_lo, x_hi, half_w, sph_c, sph_r, wall_tag, inflow_tag,
-              outer_tag, return_info, scale, ext_rings=None):
+              outer_tag, return_info, scale, ext_rings=None, cone=None):
     """Tetrahedra of the extruded O-grid.  `ext_rings` (box only) appends
-    rings beyond the outer square: a list of half-widths > half_w."""
+    rings beyond the outer square: a list of half-widths > half_w; `cone`
+    (apex x, slope) gives a circular outer boundary of radius
+    slope (x - apex x)."""
     n_ext = 0 if ext_rings is None else len(ext_rings)
     desc, per, quads = _o_grid(nt, nr1, nr2 + n_ext)
     nodes2 = len(desc)
@@ -210,6 +218,8 @@ def _assemble(kind, nt, nr1, nr2, xs, x_lo, x_hi, half_w, sph_c, sph_r, wall_tag
         R = float(_contour_radius(x, x_lo, x_hi))
         if kind == "sphere":
             outer_r = np.sqrt(max(sph_r ** 2 - (x - sph_c[0]) ** 2, 0.0))
+        elif cone is not None:
+            outer_r = cone[1] * (x - cone[0])
         for n, key in enumerate(desc):
             if key[0] == "in":
                 u = -1.0 + 2.0 * key[1] / nt
@@ -225,7 +235,7 @@ def _assemble(kind, nt, nr1, nr2, xs, x_lo, x_hi, half_w, sph_c, sph_r, wall_tag
             elif r > nr:
                 Y[ix, n] = ext_rings[r - nr - 1] * S
             else:
-                if kind == "sphere":
+                if kind == "sphere" or cone is not None:
                     O = outer_r * S / np.linalg.norm(S)
                 else:
                     O = half_w * S
@@ -248,7 +258,7 @@ def _assemble(kind, nt, nr1, nr2, xs, x_lo, x_hi, half_w, sph_c, sph_r, wall_tag
     A, B, C_ = tri_sorted[:, 0], tri_sorted[:, 1], tri_sorted[:, 2]
     tets, tet_layer, tet_tri = [], [], []
     for l in range(nx - 1):
-        if kind == "half" and xs[l] < BELL_X1 - 1e-12:
+        if kind in ("half", "half-cone") and xs[l] < BELL_X1 - 1e-12:
             sel = tri_inside
         else:
             sel = np.ones(len(tris), dtype=bool)
