@@ -1,9 +1,11 @@
 """Pins for the oracle's semi-discrete operator f(q) and its boundary states.
 
-Independent facts used: free-stream preservation, exact conservation on
-periodic and closed-wall boxes, homogeneity of degree one of the Euler flux,
-rotation invariance, the exact translating isentropic vortex (consistency of
-the whole interior operator), the algebra of the outflow and wall ghosts,
+Independent facts used, at every order the hot path runs (N = 2..5):
+free-stream preservation, exact conservation on periodic and closed-wall
+boxes (round-off scaled by the monomial Vandermonde's conditioning), the
+exact translating isentropic vortex (consistency rate in h and geometric
+convergence in N of the whole interior operator); and homogeneity of degree
+one of the Euler flux, rotation invariance, the algebra of the outflow and wall ghosts,
 the linear-acoustic response of a duct to the mouthpiece inflow, and the
 values printed in the paper.
 """
@@ -37,34 +39,53 @@ def uniform_state(mesh, phys):
     return np.broadcast_to(phys.q0[None, :, None], (mesh.K, 5, mesh.ref.Np)).copy()
 
 
-@pytest.mark.parametrize("N", [2, 3])
+def roundoff(N):
+    """FP64 round-off level of the oracle's operators at order N: the
+    monomial Vandermonde is inverted explicitly, so errors of a few eps are
+    amplified by its condition number (38, 410, 4.8e3, 5.6e4 at N = 2..5);
+    a factor 20 above eps * cond(V)."""
+    return 20.0 * np.finfo(float).eps * np.linalg.cond(ref_of(N).V)
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
 @pytest.mark.parametrize("u0", [(0.0, 0.0, 0.0), (0.3, 0.2, 0.1)])
 def test_free_stream(N, u0):
     mesh = make_mesh(N, box_kuhn(4, jitter=0.05, seed=1))
     phys = euler.Physics(u0=u0)
     r = euler.rhs(mesh, uniform_state(mesh, phys), 0.0, phys)
-    assert np.abs(r).max() < 1e-12
+    assert np.abs(r).max() < roundoff(N)
 
 
-@pytest.mark.parametrize("N", [2, 3])
+def _conservation_rates(mesh, q, phys):
+    """Rates of the conserved totals and their round-off scale (the same
+    totals of |rhs|)."""
+    r = euler.rhs(mesh, q, 0.0, phys)
+    return norms.totals(mesh, r), norms.totals(mesh, np.abs(r))
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
 def test_conservation_periodic(N):
     mesh = make_mesh(N, box_kuhn(3, jitter=0.05, seed=2, periodic=True))
     phys = euler.Physics()
     prim = gaussian_pulse(mesh.x, 0.1 * phys.p0, 0.4, center=(0.1, -0.2, 0.05))
     prim[..., 1] = 0.2 * np.sin(np.pi * mesh.x[..., 1])
     q = euler.initial_state(prim, phys.gamma)
-    rates = norms.totals(mesh, euler.rhs(mesh, q, 0.0, phys))
-    assert np.abs(rates).max() < 1e-12, rates
+    rates, scale = _conservation_rates(mesh, q, phys)
+    assert (np.abs(rates) < roundoff(N) * scale).all(), rates / scale
 
 
-def test_conservation_walls():
-    mesh = make_mesh(2, box_kuhn(3, jitter=0.05, seed=3, bc=BC_WALL))
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+def test_conservation_walls(N):
+    """Closed slip-wall box: mass and energy are conserved (the mirror
+    ghost carries no mass or energy flux); momentum is not (wall pressure)."""
+    mesh = make_mesh(N, box_kuhn(3, jitter=0.05, seed=3, bc=BC_WALL))
     phys = euler.Physics()
     prim = gaussian_pulse(mesh.x, 0.1 * phys.p0, 0.4, center=(0.1, -0.2, 0.05))
     prim[..., 1:4] = 0.1 * np.cos(mesh.x)
     q = euler.initial_state(prim, phys.gamma)
-    rates = norms.totals(mesh, euler.rhs(mesh, q, 0.0, phys))
-    assert abs(rates[0]) < 1e-13 and abs(rates[4]) < 1e-13, rates
+    rates, scale = _conservation_rates(mesh, q, phys)
+    assert (np.abs(rates[[0, 4]]) < roundoff(N) * scale[[0, 4]]).all(), rates / scale
+    assert (np.abs(rates[1:4]) > 1e-6 * scale[1:4]).any()
 
 
 def test_homogeneity():
@@ -158,11 +179,25 @@ def _vortex_residual(N, n):
     return np.sqrt(sum(norms.l2(mesh, e[:, v]) ** 2 for v in range(5)))
 
 
-@pytest.mark.parametrize("N", [2, 3])
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
 def test_vortex_consistency_rate(N):
+    """The residual f(q_exact) - dq_exact/dt of the nodal strong form is the
+    derivative of an interpolation error, O(h^N): halving h (8 -> 16 hexes
+    across the 10 x 10 period) gains at least N - 1/2 (observed 2.0, 3.2,
+    3.8, 5.2 at N = 2..5)."""
     e1, e2 = _vortex_residual(N, 8), _vortex_residual(N, 16)
     rate = np.log2(e1 / e2)
     assert rate > N - 0.5, (e1, e2, rate)
+
+
+def test_vortex_p_convergence():
+    """On a fixed mesh (12 x 12 hexes across the period) the same residual
+    falls at least geometrically with the order: each order at least halves
+    it (observed ratios 0.33, 0.28, 0.33 from N = 2 to 5), so it decreases
+    monotonically -- spectral convergence of the smooth solution."""
+    e = [_vortex_residual(N, 12) for N in (2, 3, 4, 5)]
+    ratios = [e[i + 1] / e[i] for i in range(3)]
+    assert all(r < 0.5 for r in ratios), (e, ratios)
 
 
 def test_outflow_ghost_algebra():
