@@ -337,6 +337,25 @@ int dg_mlp_set_params(dg_mlp* m, const float* params, void* stream);
  * workspace the first time a larger B is seen). */
 int dg_mlp_infer(dg_mlp* m, const float* X, float* Y, int64_t B, int bf16, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP32
+ * forward of dg_mlp_infer(m, X, Y, B, 0, stream), with the same kernels and
+ * bitwise the same Y, whose hidden activations live in a fixed device array
+ * of the library instead of a workspace it allocates.  The array holds
+ * DG_MLP_NOALLOC_ROWS rows (4 x 128 FP32 each, 8 MiB in all); each GPU the
+ * library runs on keeps its own copy until the process ends.  X [B][78],
+ * Y [B][75]: device pointers on the current device (the one m was created
+ * on), caller-owned; B = 0 does nothing and reads neither pointer.  Calls no
+ * hipMalloc or hipFree.  Errors: DG_EINVAL for a null pointer (B > 0),
+ * B < 0 or B > DG_MLP_NOALLOC_ROWS; DG_EHIP if the array's
+ * address cannot be obtained or a launch fails.  Every call on one GPU shares
+ * that GPU's array (nothing in it needs to start at zero; each call
+ * overwrites what it reads): calls that overlap on one GPU, from two streams
+ * or two host threads, race, and the caller must order them.  Asynchronous
+ * on stream. */
+#define DG_MLP_NOALLOC_ROWS 4096
+int dg_mlp_infer_noalloc(dg_mlp* m, const float* X, float* Y, int64_t B, void* stream);
+
 /* Loss and gradient for rows (X [B][78], Y [B][75]) (device): grads is a
  * device FP32 [DG_MLP_PARAMS] (NULL: internal); *loss (host, optional) is
  * read back with a synchronization.  Deterministic. */

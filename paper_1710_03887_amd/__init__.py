@@ -16,4 +16,4 @@ from ._lib import (Context, DGError, EXPORTED, dg_mesh_setup, dg_destroy, dg_las
                    dg_mlp_set_params, dg_mlp_infer, dg_mlp_grad, dg_mlp_train_step,
                    dg_set_learned_bc, dg_learned_faces, dg_sample_traces, dg_set_kernel,
                    dg_get_kernel, dg_probe_setup, dg_probe_sample, dg_run_probes, dg_spectrum,
-                   dg_set_damping, dg_set_curved)
+                   dg_set_damping, dg_set_curved, dg_mlp_infer_noalloc, DG_MLP_NOALLOC_ROWS)

@@ -18,6 +18,7 @@ DG_BC_INTERIOR, DG_BC_OUTFLOW_CHAR, DG_BC_PASSTHRU, DG_BC_WALL, DG_BC_INFLOW, DG
 DG_FP32, DG_SPLIT_BF16 = 0, 1
 DG_SETUP_HOST_ONLY = 1
 DG_SETUP_QUADRATURE = 2
+DG_MLP_NOALLOC_ROWS = 4096
 
 _ERRNAMES = {DG_EINVAL: "DG_EINVAL", DG_EMESH: "DG_EMESH", DG_ENOMEM: "DG_ENOMEM",
              DG_EHIP: "DG_EHIP", DG_ENONPHYS: "DG_ENONPHYS", DG_ENODEV: "DG_ENODEV"}
@@ -81,6 +82,7 @@ _SIGS = {
     "dg_mlp_get_params": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_mlp_set_params": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_mlp_infer": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int, _vp]),
+    "dg_mlp_infer_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp]),
     "dg_mlp_grad": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(ctypes.c_float), _vp, _vp]),
     "dg_mlp_train_step": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, ctypes.c_float,
                                          ctypes.POINTER(ctypes.c_float), _vp]),
@@ -582,6 +584,13 @@ def dg_mlp_infer(m, X, Y, bf16=True, stream=None):
     _check_dev(X, (B, MLP_IN), "torch.float32", "X")
     _check_dev(Y, (B, MLP_OUT), "torch.float32", "Y")
     _mcheck(_lib.dg_mlp_infer(m.handle, _ptr(X), _ptr(Y), B, 1 if bf16 else 0, _stream(stream)), m)
+
+
+def dg_mlp_infer_noalloc(m, X, Y, stream=None):
+    B = X.shape[0]
+    _check_dev(X, (B, MLP_IN), "torch.float32", "X")
+    _check_dev(Y, (B, MLP_OUT), "torch.float32", "Y")
+    _mcheck(_lib.dg_mlp_infer_noalloc(m.handle, _ptr(X), _ptr(Y), B, _stream(stream)), m)
 
 
 def dg_mlp_grad(m, X, Y, grads=None, stream=None):

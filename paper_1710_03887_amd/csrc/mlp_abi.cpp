@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -64,6 +65,34 @@ int read_loss(dg_mlp* m, float* loss, hipStream_t s) {
   hipError_t e = hipMemcpyAsync(loss, m->loss_dev, sizeof(float), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e == hipSuccess ? DG_OK : mfail(m, DG_EHIP, hipGetErrorString(e));
+}
+
+// Fixed activation storage of dg_mlp_infer_noalloc: z1, a1, z2, a2 of up to
+// DG_MLP_NOALLOC_ROWS rows.  In host code `scratch` only names the symbol;
+// its device address comes from hipGetSymbolAddress, once per device.
+constexpr int64_t kNoAllocRows = DG_MLP_NOALLOC_ROWS;
+constexpr size_t kScratchFloats = size_t(kNoAllocRows) * 4 * dg::kMlpH;
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+float* scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+hipError_t scratch_address(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_dev[dev] = static_cast<float*>(p);
+  }
+  *out = scratch_dev[dev];
+  return hipSuccess;
 }
 
 }  // namespace
@@ -151,6 +180,28 @@ int dg_mlp_infer(dg_mlp* m, const float* X, float* Y, int64_t B, int bf16, void*
     e = ensure_cap(m, B);
     if (e == hipSuccess) e = dg::mlp_forward_f32(m->P, X, B, m->w, Y, s);
   }
+  return e == hipSuccess ? DG_OK : mfail(m, DG_EHIP, hipGetErrorString(e));
+}
+
+int dg_mlp_infer_noalloc(dg_mlp* m, const float* X, float* Y, int64_t B, void* stream) {
+  if (!m) return DG_EINVAL;
+  if (B == 0) return DG_OK;  // nothing to do; X and Y are not read
+  if (!X || !Y || B < 0) return mfail(m, DG_EINVAL, "null pointer or negative row count");
+  if (B > kNoAllocRows)
+    return mfail(m, DG_EINVAL, "dg_mlp_infer_noalloc: B = " + std::to_string(B) +
+                                   " exceeds DG_MLP_NOALLOC_ROWS = " + std::to_string(kNoAllocRows));
+  float* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess)
+    return mfail(m, DG_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+  // the same four activation arrays as the allocated workspace, packed at B rows
+  dg::MlpWork w;
+  w.cap = B;
+  w.z1 = base;
+  w.a1 = base + B * dg::kMlpH;
+  w.z2 = base + 2 * B * dg::kMlpH;
+  w.a2 = base + 3 * B * dg::kMlpH;
+  e = dg::mlp_forward_f32(m->P, X, B, w, Y, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? DG_OK : mfail(m, DG_EHIP, hipGetErrorString(e));
 }
 
