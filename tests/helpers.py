@@ -37,6 +37,7 @@ class Pair:
 
     def __init__(self, m, N, phys, precision=dg.DG_FP32):
         self.ref = ref_of(N)
+        self.bc = np.asarray(m["bc"])
         self.mesh = Mesh(self.ref, m["xyz"], m["EToV"], m["bc"])
         self.phys = phys
         self.ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, precision=precision,
@@ -111,3 +112,52 @@ def rel_l2_rows(mesh, rows, a, b):
               for v in range(5))
     den = sum(np.sum(J * np.einsum("ki,ij,kj->k", b[:, v], M, b[:, v])) for v in range(5))
     return float(np.sqrt(num / den))
+
+
+# ---- node-by-node comparison ---------------------------------------------------
+
+TAG_NAMES = {1: "char_outflow", 2: "pass_through", 3: "wall", 4: "inflow", 5: "learned"}
+VAR_NAMES = ("rho", "rho_u", "rho_v", "rho_w", "E")
+TILE = 16   # elements per tile of the library's stage kernel
+
+
+def element_groups(bc, tile=TILE):
+    """Element index sets that a localized defect would show up in: every
+    element, elements whose four faces are interior, elements with a face of
+    each boundary tag present, and the last tile of `tile` consecutive
+    elements (partial when K is not a multiple of it)."""
+    bc = np.asarray(bc)
+    K = bc.shape[0]
+    groups = {"all": np.arange(K)}
+    inner = np.nonzero((bc == _BC_INTERIOR).all(axis=1))[0]
+    if inner.size:
+        groups["interior"] = inner
+    for tag, name in TAG_NAMES.items():
+        rows = np.nonzero((bc == tag).any(axis=1))[0]
+        if rows.size:
+            groups[name] = rows
+    groups["last_tile"] = np.arange((K - 1) // tile * tile, K)
+    return groups
+
+
+def nodewise_errors(a, b, groups):
+    """{group: [5]} max over the group's nodes of |a - b| per variable,
+    relative to that variable's largest |b| over every element."""
+    scale = np.abs(b).max(axis=(0, 2))
+    scale = np.where(scale > 0, scale, 1.0)
+    return {g: np.abs(a[rows] - b[rows]).max(axis=(0, 2)) / scale for g, rows in groups.items()}
+
+
+def assert_nodewise(a, b, bc, bar, label=""):
+    """Node-by-node parity: every variable at every node of every group
+    within `bar` of the reference (relative to the variable's max |ref|).
+    Prints the table; returns the largest error."""
+    errs = nodewise_errors(a, b, element_groups(bc))
+    worst = 0.0
+    for g, e in errs.items():
+        print(f"  {label} nodewise {g:>13s}: " + " ".join(f"{v}={x:.2e}" for v, x in
+                                                          zip(VAR_NAMES, e)), flush=True)
+        worst = max(worst, float(e.max()))
+    bad = {g: float(e.max()) for g, e in errs.items() if not (e.max() < bar)}
+    assert not bad, f"{label} nodewise error above {bar:g} in {bad}"
+    return worst

@@ -6,8 +6,13 @@ itself rounded to 8 significant bits) and dropping lo*lo, each product
 D_ij F_j is off by at most ~3 * 2^-16 |D_ij F_j|; summed over the Np x 3Np
 contraction with the cancellation a derivative has (|sum D F| is ~h^-1 |F|
 while sum |D| |F| is ~h^-1 (N+1)^2 |F|), one right-hand side is within
-~3 * 2^-16 (N+1)^2 ~ 1e-3 relative at N = 4; the bar is 2e-3 for one
-evaluation and the method's 1e-3 relative L2 of p' after 100 steps.
+~3 * 2^-16 (N+1)^2 ~ 1e-3 relative at N = 4 in the worst case of aligned
+rounding.  The rounding errors are not aligned: 1e-5 relative L2 is observed
+(N = 1..5 and the 1.17M-tet N = 5 mesh), so one evaluation is held to 2e-4
+relative L2 and, node by node (per variable, per element group: all,
+all-interior, each boundary tag, the last partial tile; relative to the
+variable's largest value), to 1e-3; 100 steps to the method's 1e-3 relative
+L2 of p'.
 """
 import numpy as np
 import pytest
@@ -15,7 +20,10 @@ import pytest
 import paper_1710_03887_amd as dg
 from oracle import euler, timestep, norms
 from workloads import box_kuhn, gaussian_pulse
-from helpers import Pair, rel_l2
+from helpers import Pair, rel_l2, assert_nodewise
+
+BF16_L2_BAR = 2e-4
+BF16_NODE_BAR = 1e-3
 
 pytestmark = pytest.mark.gpu
 
@@ -39,9 +47,11 @@ def test_rhs_parity_bf16(N):
     rd = torch.empty_like(qd)
     dg.dg_rhs(pair.ctx, qd, rd, 0.0)
     torch.cuda.synchronize()
-    err = rel_l2(pair.mesh, pair.rates_from_device(rd), r_or)
+    r_gpu = pair.rates_from_device(rd)
+    err = rel_l2(pair.mesh, r_gpu, r_or)
     print(f"N={N} split-BF16 rhs rel L2 {err:.3e}")
-    assert err < 2e-3
+    assert err < BF16_L2_BAR
+    assert_nodewise(r_gpu, r_or, pair.bc, BF16_NODE_BAR, f"N={N} bf16")
 
 
 @pytest.mark.parametrize("amp", [0.005, 0.02, 0.1])

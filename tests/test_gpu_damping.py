@@ -1,7 +1,7 @@
 """The absorbing layer (dg_set_damping) against the FP64 oracle's
-rhs - sigma (q - q0), with the bars of the plain operator (2e-5 relative L2
-for one FP32 right-hand side, 2e-3 split-BF16, 1e-5 for p' after 100
-steps).  A context set to the wavefront-private kernel runs the
+rhs - sigma (q - q0), with the bars of the plain operator (one right-hand
+side: FP32 3e-6 relative L2 and 1e-5 node by node per element group,
+split-BF16 2e-4 and 1e-3; 1e-5 for p' after 100 steps).  A context set to the wavefront-private kernel runs the
 tile-cooperative one while a layer is set (checked through the same bars)."""
 import numpy as np
 import pytest
@@ -10,7 +10,7 @@ import paper_1710_03887_amd as dg
 from oracle import euler, timestep, norms
 from workloads import (box_kuhn, gaussian_pulse, BC_OUTFLOW_CHAR, BC_WALL, BC_INFLOW,
                        BC_PASSTHRU)
-from helpers import Pair, rel_l2
+from helpers import Pair, rel_l2, assert_nodewise
 
 pytestmark = pytest.mark.gpu
 
@@ -47,10 +47,13 @@ def test_rhs_parity_with_layer(N, variant, precision):
     dg.dg_rhs(pair.ctx, qd, rd, 0.13)
     torch.cuda.synchronize()
     r_or = euler.rhs(pair.mesh, q, 0.13, phys, sigma=sig)
-    err = rel_l2(pair.mesh, pair.rates_from_device(rd), r_or)
-    tol = 2e-3 if precision == dg.DG_SPLIT_BF16 else 2e-5
+    got = pair.rates_from_device(rd)
+    err = rel_l2(pair.mesh, got, r_or)
+    tol = 2e-4 if precision == dg.DG_SPLIT_BF16 else 3e-6
     print(f"N={N} variant {variant} precision {precision}: rhs with layer rel L2 {err:.3e}")
     assert err < tol
+    assert_nodewise(got, r_or, pair.bc, 1e-3 if precision == dg.DG_SPLIT_BF16 else 1e-5,
+                    f"layer N={N}")
     # the layer's term is really there (the plain operator differs by far more than the bar
     # of the FP32 form)
     assert rel_l2(pair.mesh, pair.rates_from_device(rd), euler.rhs(pair.mesh, q, 0.13, phys)) > 1e-2

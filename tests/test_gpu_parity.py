@@ -1,11 +1,17 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
-Tolerances come from FP32 arithmetic: one right-hand side is a sum of
-~3 Np + 4 Nfp products of O(1) operator entries with flux perturbations,
-so its rounding error is a few FP32 ulps (6e-8) times that length relative
-to the flux scale; the bar for one evaluation is 2e-5 relative L2, and the
-bar for 100 steps is the 1e-5 relative L2 of the pressure perturbation that
-the method's FP32 form is specified to meet.
+One right-hand side is checked two ways.  (1) Relative L2 over all
+variables, bar 3e-6: each output is a sum of ~3 Np + 4 Nfp FP32 products of
+O(1) operator entries with flux perturbations plus the flux arithmetic, so
+its rounding is a few FP32 ulps (6e-8) times the square root of that length
+relative to the flux scale; 2-3e-7 is observed at N = 1..5, and the bar
+leaves a factor of ten.  (2) Node by node: per variable, the largest error
+over the nodes of every element, of the all-interior elements, of the
+elements on each boundary tag and of the last (partial) tile, relative to
+the variable's largest value, bar 1e-5 -- a defect confined to one face
+orientation, one boundary kind or one tile is O(1) there, far above the bar.
+After 100 steps the bar is the 1e-5 relative L2 of the pressure perturbation
+that the method's FP32 form is specified to meet.
 """
 import numpy as np
 import pytest
@@ -14,7 +20,10 @@ import paper_1710_03887_amd as dg
 from oracle import euler, timestep, norms
 from workloads import (box_kuhn, gaussian_pulse, BC_OUTFLOW_CHAR, BC_WALL, BC_INFLOW,
                        BC_PASSTHRU)
-from helpers import Pair, rel_l2
+from helpers import Pair, rel_l2, assert_nodewise
+
+RHS_L2_BAR = 3e-6
+RHS_NODE_BAR = 1e-5
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +51,8 @@ def test_rhs_parity_box(N):
     r_gpu = pair.rates_from_device(rd)
     err = rel_l2(pair.mesh, r_gpu, r_or)
     print(f"N={N} rhs rel L2 {err:.3e}")
-    assert err < 2e-5
+    assert err < RHS_L2_BAR
+    assert_nodewise(r_gpu, r_or, pair.bc, RHS_NODE_BAR, f"N={N}")
 
 
 @pytest.mark.parametrize("N", [2, 4])
@@ -60,9 +70,11 @@ def test_rhs_parity_all_boundary_kinds(N):
     rd = torch.empty_like(qd)
     dg.dg_rhs(pair.ctx, qd, rd, t)
     torch.cuda.synchronize()
-    err = rel_l2(pair.mesh, pair.rates_from_device(rd), r_or)
+    r_gpu = pair.rates_from_device(rd)
+    err = rel_l2(pair.mesh, r_gpu, r_or)
     print(f"N={N} mixed-boundary rhs rel L2 {err:.3e}")
-    assert err < 2e-5
+    assert err < RHS_L2_BAR
+    assert_nodewise(r_gpu, r_or, pair.bc, RHS_NODE_BAR, f"N={N} mixed")
 
 
 def test_partial_tile_and_single_element():
@@ -76,8 +88,11 @@ def test_partial_tile_and_single_element():
         rd = torch.full_like(qd, float("nan"))
         dg.dg_rhs(pair.ctx, qd, rd, 0.0)
         torch.cuda.synchronize()
-        err = rel_l2(pair.mesh, pair.rates_from_device(rd), r_or)
-        assert err < 2e-5, (n, err)
+        r_gpu = pair.rates_from_device(rd)
+        err = rel_l2(pair.mesh, r_gpu, r_or)
+        print(f"{n} hexes ({pair.mesh.K} tets): rhs rel L2 {err:.3e}")
+        assert err < RHS_L2_BAR, (n, err)
+        assert_nodewise(r_gpu, r_or, pair.bc, RHS_NODE_BAR, f"{pair.mesh.K} tets")
 
 
 def test_step_parity():

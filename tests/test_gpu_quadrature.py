@@ -1,7 +1,10 @@
 """The quadrature scheme (DG_SETUP_QUADRATURE: weak form with Gauss
 quadrature, RK2) on the GPU against its FP64 oracle (oracle/quadrature.py),
-with the bars of the nodal scheme: 2e-5 relative L2 for one right-hand side,
-1e-5 for p' after 100 steps; free stream to FP32 rounding."""
+one right-hand side within 5e-6 relative L2 (7e-7 observed: the quadrature
+sums are longer than the nodal scheme's, (N+1)^3 volume and 7 face points per
+term) and 3e-5 node by node per element group (all, all-interior, each
+boundary tag, the last partial tile), p' after 100 steps within 1e-5; free
+stream to FP32 rounding."""
 import numpy as np
 import pytest
 
@@ -11,7 +14,7 @@ from oracle.mesh import Mesh
 from oracle.quadrature import QuadScheme
 from workloads import (box_kuhn, trumpet_domain, gaussian_pulse, BC_OUTFLOW_CHAR, BC_WALL,
                        BC_INFLOW, BC_PASSTHRU)
-from helpers import ref_of, node_perm, phys_kwargs, rel_l2
+from helpers import ref_of, node_perm, phys_kwargs, rel_l2, assert_nodewise
 
 pytestmark = pytest.mark.gpu
 
@@ -21,6 +24,7 @@ torch = pytest.importorskip("torch")
 class QPair:
     def __init__(self, m, N, phys):
         self.ref = ref_of(N)
+        self.bc = np.asarray(m["bc"])
         self.mesh = Mesh(self.ref, m["xyz"], m["EToV"], m["bc"])
         self.phys = phys
         self.scheme = QuadScheme(self.mesh)
@@ -57,9 +61,11 @@ def test_rhs_parity_all_boundary_kinds(N):
     dg.dg_rhs(pair.ctx, pair.to_device(q), rd, 0.13)
     torch.cuda.synchronize()
     r_or = pair.scheme.rhs(q, 0.13, phys)
-    err = rel_l2(pair.mesh, pair.from_device(rd, perturbation=False), r_or)
+    got = pair.from_device(rd, perturbation=False)
+    err = rel_l2(pair.mesh, got, r_or)
     print(f"N={N} quadrature rhs rel L2 {err:.3e}")
-    assert err < 2e-5
+    assert err < 5e-6
+    assert_nodewise(got, r_or, pair.bc, 3e-5, f"quadrature N={N}")
     # it is not the nodal scheme's right-hand side
     assert rel_l2(pair.mesh, r_or, euler.rhs(pair.mesh, q, 0.13, phys)) > 1e-4
 
@@ -71,9 +77,11 @@ def test_rhs_parity_trumpet_n2():
     rd = torch.empty_like(pair.to_device(q))
     dg.dg_rhs(pair.ctx, pair.to_device(q), rd, 0.2)
     torch.cuda.synchronize()
-    err = rel_l2(pair.mesh, pair.from_device(rd, perturbation=False), pair.scheme.rhs(q, 0.2, phys))
+    got, r_or = pair.from_device(rd, perturbation=False), pair.scheme.rhs(q, 0.2, phys)
+    err = rel_l2(pair.mesh, got, r_or)
     print(f"trumpet N=2 quadrature rhs rel L2 {err:.3e}")
-    assert err < 2e-5
+    assert err < 5e-6
+    assert_nodewise(got, r_or, pair.bc, 3e-5, "quadrature trumpet N=2")
 
 
 def test_free_stream():
