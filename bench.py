@@ -175,6 +175,24 @@ def time_single(dg, torch, m, N, form, steps, warmup, kernel_iters):
                       f"<{N},MODE_STAGE>"}
 
 
+def stage_only(dg, torch, m, N, form, launches):
+    """Launches of the fused stage kernel alone on a small random state
+    (for profiler counters): no autotuning, no other kernels in between."""
+    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, gamma=1.4, rho0=1.0, p0=1.0 / 1.4,
+                           inflow_amp=0.1 / 1.4, inflow_alpha=2 * np.pi * 565.0 / 343.0,
+                           precision={"fp32": dg.DG_FP32, "bf16": dg.DG_SPLIT_BF16}[form])
+    dev = torch.device("cuda", 0)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    q = (1e-3 * torch.randn((ctx.K, 5, ctx.Np), generator=g)).to(dev)
+    res, qb = torch.zeros_like(q), torch.empty_like(q)
+    for i in range(launches):
+        src, dst = (q, qb) if i % 2 == 0 else (qb, q)
+        dg.dg_stage(ctx, src, dst, res, RK4A2, RK4B2, 0.1, 1e-5)
+    torch.cuda.synchronize()
+    print(json.dumps({"stage_only": launches, "K": ctx.K, "N": N, "form": form,
+                      "kernel_variant": dg.dg_get_kernel(ctx)}), flush=True)
+
+
 def batch_stage_bytes(Ks, Np, members=16):
     """Algorithmic HBM bytes of one batched stage: four FP32 state passes
     per member-innermost DOF plus each element's geometry and connectivity
@@ -433,6 +451,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--stage-only", type=int, default=0, metavar="LAUNCHES",
+                    help="counter-collection mode: set up the workload and launch only the "
+                         "fused stage kernel this many times (default launch shape), then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the element-partitioned multi-GPU path "
@@ -446,6 +467,9 @@ def main():
 
     m = trumpet_domain("box", args.elements)
     N = args.order
+    if args.stage_only:
+        stage_only(dg, torch, m, N, args.form, args.stage_only)
+        return
     r = time_single(dg, torch, m, N, args.form, args.steps, args.warmup, args.kernel_iters)
     K, Np = r["K"], r["Np"]
     traffic = measured_traffic(args.form, K)
