@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SEGMENTS = 5    # timed steps are split into this many event-timed dg_run calls
 RK4A2, RK4B2 = -567301805773.0 / 1357537059087.0, 5161836677717.0 / 13612068292357.0
 
 
@@ -42,7 +43,7 @@ def kernel_source_hash():
     """Hash of the stage kernel's sources and compile flags."""
     import importlib.util
     h = hashlib.sha256()
-    for name in ("csrc/kernels.hip", "csrc/physics.hpp", "csrc/kernels.hpp"):
+    for name in ("csrc/kernels.hip", "csrc/spec_stage.hip", "csrc/physics.hpp", "csrc/kernels.hpp"):
         with open(os.path.join(ROOT, "paper_1710_03887_amd", name), "rb") as f:
             h.update(f.read())
     spec = importlib.util.spec_from_file_location(
@@ -53,9 +54,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(form, K):
+def measured_traffic(form, K, variant):
     """HBM bytes per stage launch from the committed rocprofv3 counter
-    summary, or None when absent or taken on a different kernel source."""
+    summary, or None when absent or taken on a different kernel source,
+    workload size or stage-kernel variant."""
     path = os.path.join(ROOT, "profiles", "stage_traffic.json")
     if not os.path.exists(path):
         return None
@@ -63,7 +65,8 @@ def measured_traffic(form, K):
         rec = json.load(open(path)).get(form)
     except (ValueError, OSError):
         return None
-    if not rec or rec.get("kernel_hash") != kernel_source_hash() or rec.get("K") != K:
+    if (not rec or rec.get("kernel_hash") != kernel_source_hash() or rec.get("K") != K
+            or rec.get("variant") != variant):
         return None
     return rec.get("bytes_per_launch")
 
@@ -82,22 +85,25 @@ def cpu_baseline(seconds_budget=30.0):
     phys = euler.Physics(amp=0.1 / 1.4, alpha=2 * np.pi * 565.0 / 343.0)
     q = np.broadcast_to(phys.q0[None, :, None], (mesh.K, 5, ref.Np)).copy()
     dt = timestep.stable_dt(mesh, q, phys, 0.5)
-    t0 = time.perf_counter()
-    stages = 0
-    while True:
-        q, _ = timestep.lserk_step(lambda y, t: euler.rhs(mesh, y, t, phys), q, 0.0, dt)
-        stages += 5
-        if time.perf_counter() - t0 > seconds_budget / 3:
-            break
-    el = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    # the same right-hand side on one BLAS thread (two evaluations)
+    # the oracle's contractions are small matrix products and its gathers are
+    # NumPy indexing: it runs at the same rate on one thread as on the whole
+    # BLAS pool, so the baseline is taken on one thread (cores = 1), with a
+    # shorter run on the full pool beside it
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
-        t1 = time.perf_counter()
-        for _ in range(2):
-            euler.rhs(mesh, q, 0.0, phys)
-        el1 = time.perf_counter() - t1
+        t0 = time.perf_counter()
+        stages = 0
+        while True:
+            q, _ = timestep.lserk_step(lambda y, t: euler.rhs(mesh, y, t, phys), q, 0.0, dt)
+            stages += 5
+            if time.perf_counter() - t0 > seconds_budget / 3:
+                break
+        el = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    for _ in range(2):
+        euler.rhs(mesh, q, 0.0, phys)
+    el1 = time.perf_counter() - t1
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -107,13 +113,14 @@ def cpu_baseline(seconds_budget=30.0):
     except OSError:
         pass
     out = {"value": 5 * mesh.K * ref.Np * stages / el, "unit": "DOF-stage updates/s",
-           "cores": int(threads), "kind": "oracle",
+           "cores": 1, "kind": "oracle",
            "sample": f"trumpet-in-box {mesh.K} tets, N=4, {stages // 5} LSERK step(s) "
-                     f"({stages} RHS evaluations) in {el:.1f} s, FP64 NumPy, "
-                     f"BLAS threads={threads}, host cores={os.cpu_count()}, CPU {model or 'unknown'}"}
-    one = {"value": 5 * mesh.K * ref.Np * 2 / el1, "unit": "DOF-stage updates/s", "threads": 1,
-           "sample": f"2 RHS evaluations of the same sample in {el1:.1f} s"}
-    return out, one
+                     f"({stages} RHS evaluations) in {el:.1f} s, FP64 NumPy on one thread, "
+                     f"host cores={os.cpu_count()}, CPU {model or 'unknown'}"}
+    pool = {"value": 5 * mesh.K * ref.Np * 2 / el1, "unit": "DOF-stage updates/s",
+            "threads": int(threads),
+            "sample": f"2 RHS evaluations of the same sample in {el1:.1f} s on {threads} BLAS threads"}
+    return out, pool
 
 
 def time_single(dg, torch, m, N, form, steps, warmup, kernel_iters):
@@ -131,29 +138,41 @@ def time_single(dg, torch, m, N, form, steps, warmup, kernel_iters):
 
     t, _ = dg.dg_run(ctx, q, res, warmup, 0.5, 0.0, stream=stream)
     torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # exactly `steps` timed steps, as SEGMENTS back-to-back dg_run calls each
+    # bracketed by HIP events on the stream they run on
+    seg = [steps // SEGMENTS + (1 if i < steps % SEGMENTS else 0) for i in range(SEGMENTS)]
+    seg = [n for n in seg if n > 0]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in seg]
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    start.record(stream)
-    t_end, dt_last = dg.dg_run(ctx, q, res, steps, 0.5, t, stream=stream)
-    stop.record(stream)
+    t_end, dt_last = t, 0.0
+    for (e0, e1), n in zip(ev, seg):
+        e0.record(stream)
+        t_end, dt_last = dg.dg_run(ctx, q, res, n, 0.5, t_end, stream=stream)
+        e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    ms = start.elapsed_time(stop)
+    seg_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    ms = sum(seg_ms)
     dof = 5 * K * Np
+    seg_rate = [dof * 5 * n / (x * 1e-3) for n, x in zip(seg, seg_ms)]
 
-    # dominant kernel: the fused stage, timed alone on the same stream
+    # dominant kernel: the fused stage, timed alone on the same stream,
+    # SEGMENTS batches of kernel_iters launches (median reported)
     qb = torch.empty_like(q)
     for _ in range(3):
         dg.dg_stage(ctx, q, qb, res, RK4A2, RK4B2, t_end, dt_last, stream=stream)
-    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    k0.record(stream)
-    for i in range(kernel_iters):
-        src, dst = (q, qb) if i % 2 == 0 else (qb, q)
-        dg.dg_stage(ctx, src, dst, res, RK4A2, RK4B2, t_end, dt_last, stream=stream)
-    k1.record(stream)
-    torch.cuda.synchronize()
-    kernel_s = k0.elapsed_time(k1) * 1e-3 / kernel_iters
+    batches = []
+    for _ in range(SEGMENTS):
+        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0.record(stream)
+        for i in range(kernel_iters):
+            src, dst = (q, qb) if i % 2 == 0 else (qb, q)
+            dg.dg_stage(ctx, src, dst, res, RK4A2, RK4B2, t_end, dt_last, stream=stream)
+        k1.record(stream)
+        torch.cuda.synchronize()
+        batches.append(k0.elapsed_time(k1) * 1e-3 / kernel_iters)
+    kernel_s = float(np.median(batches))
     # dg_rhs alone (q in, rhs out: 40 Np + 220 algorithmic bytes per element)
     r = torch.empty_like(q)
     r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -168,10 +187,14 @@ def time_single(dg, torch, m, N, form, steps, warmup, kernel_iters):
     variant = dg.dg_get_kernel(ctx)
     return {"K": K, "N": N, "Np": Np, "dof": dof, "ms": ms, "wall_s": wall, "t_end": t_end,
             "dt_last": dt_last, "value": dof * 5 * steps / (ms * 1e-3), "kernel_s": kernel_s,
+            "segments": {"steps": seg, "ms": seg_ms, "median_value": float(np.median(seg_rate)),
+                         "min_value": min(seg_rate), "max_value": max(seg_rate),
+                         "spread": (max(seg_rate) - min(seg_rate)) / float(np.median(seg_rate))},
+            "kernel_batches_ms": [b * 1e3 for b in batches],
             "bytes": nbytes, "achieved": nbytes / kernel_s / 1e9, "blocks_per_cu": bpc,
             "kernel_variant": variant,
             "rhs_ms": rhs_s * 1e3, "rhs_GBs": rhs_bytes / rhs_s / 1e9,
-            "kernel": ("stage_kernel" if variant == 0 else "wave_stage_kernel") +
+            "kernel": ("stage_kernel" if variant == 0 else "spec_stage_kernel") +
                       f"<{N},MODE_STAGE>"}
 
 
@@ -472,7 +495,7 @@ def main():
         return
     r = time_single(dg, torch, m, N, args.form, args.steps, args.warmup, args.kernel_iters)
     K, Np = r["K"], r["Np"]
-    traffic = measured_traffic(args.form, K)
+    traffic = measured_traffic(args.form, K, r["kernel_variant"])
     extra = {}
     for name in [x for x in args.also.split(",") if x]:
         if name in ("fp32", "bf16") and name != args.form:
@@ -482,7 +505,7 @@ def main():
                            "speedup_vs_headline": o["value"] / r["value"],
                            "stage_kernel_ms": o["kernel_s"] * 1e3,
                            "stage_GBs": o["achieved"], "frac": o["achieved"] / HBM_PEAK_GBS,
-                           "traffic": measured_traffic(name, K)}
+                           "traffic": measured_traffic(name, K, o["kernel_variant"])}
         elif name == "batch":
             extra["batch"] = time_batch(dg, torch, args.batch_steps, 4, 10)
         elif name == "n5":
@@ -520,12 +543,14 @@ def main():
                                "inflow pulse 0.1 p0, characteristic outflow, slip walls",
                    "K": K, "N": N, "Np": Np, "dof": r["dof"], "form": args.form,
                    "t_end": r["t_end"], "dt_last": r["dt_last"], "wall_s": r["wall_s"],
-                   "blocks_per_cu": r["blocks_per_cu"], "kernel_variant": r["kernel_variant"]},
+                   "blocks_per_cu": r["blocks_per_cu"], "kernel_variant": r["kernel_variant"],
+                   "segments": r["segments"]},
         "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
                                      "copy-calibrated)",
                      "kernel": r["kernel"], "kernel_ms": r["kernel_s"] * 1e3,
+                     "kernel_ms_batches": r["kernel_batches_ms"],
                      "bytes_per_launch": r["bytes"],
                      "dg_rhs": {"ms": r["rhs_ms"], "achieved": r["rhs_GBs"],
                                 "frac": r["rhs_GBs"] / HBM_PEAK_GBS,
@@ -533,7 +558,7 @@ def main():
         "forms": extra,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], out["forms"]["oracle_one_thread"] = cpu_baseline()
+        out["cpu_baseline"], out["forms"]["oracle_blas_pool"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

@@ -280,15 +280,17 @@ int dg_set_launch(dg_ctx* ctx, int blocks_per_cu);
 
 /* Stage kernel of a single-solve context: 0 = tile-cooperative (four
  * wavefronts share a 16-element tile and split the contraction), 1 =
- * wavefront-private (each wavefront owns a 16-element tile; FP32 form,
- * N <= 4).  Same results up to floating-point summation order.  Used by the
- * autotuner; DG_EINVAL when the variant does not apply. */
+ * role-specialized (per block, four surface wavefronts form the face jumps
+ * of one tile while four contraction wavefronts, holding the operator in
+ * registers, run the products and the RK update of the previous tile; FP32
+ * form, N <= 4).  Same results up to floating-point summation order.  Used
+ * by the autotuner; DG_EINVAL when the variant does not apply. */
 int dg_set_kernel(dg_ctx* ctx, int variant);
 int dg_get_kernel(const dg_ctx* ctx);
 
 /* ---- launch-shape autotuner -------------------------------------------------
  * Times every launch shape of the stage kernel (resident blocks per CU, and
- * the stage-kernel variant where the wavefront-private one applies; for
+ * the stage-kernel variant where the role-specialized one applies; for
  * batches blocks per CU and wavefronts per block) on the caller's stream
  * with HIP events,
  * applies the fastest and appends it to the text cache at cache_path (NULL or
@@ -406,8 +408,8 @@ int dg_sample_traces(dg_ctx* ctx, const float* q, const int64_t* faces, int64_t 
  * library's node order (see dg_nodes), borrowed: it must stay valid while the
  * context uses it; NULL turns the layer off.  Applies to dg_rhs, dg_step,
  * dg_stage and the runs of this context (not to batches: dg_batch_create
- * rejects a context with a layer).  While a layer is set the
- * tile-cooperative stage kernel runs whatever dg_set_kernel chose.  Errors:
+ * rejects a context with a layer).  Both stage-kernel variants apply
+ * it.  Errors:
  * DG_ENODEV on a host-only context. */
 int dg_set_damping(dg_ctx* ctx, const float* sigma);
 

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["setup.cpp", "abi.cpp", "batch_abi.cpp", "autotune.cpp", "mlp_abi.cpp", "kernels.hip", "curved.hip",
-           "wave_stage.hip", "batch.hip", "mlp.hip", "probes.hip", "quad.hip"]
+           "spec_stage.hip", "batch.hip", "mlp.hip", "probes.hip", "quad.hip"]
 LIB = os.path.join(HERE, "libdg.so")
 ARCH = os.environ.get("DG_OFFLOAD_ARCH", "gfx950")
 

@@ -568,8 +568,8 @@ int dg_set_kernel(dg_ctx* c, int variant) {
   int rc = need_device(c);
   if (rc) return rc;
   if (variant != 0 && variant != 1) return fail(c, DG_EINVAL, "variant must be 0 or 1");
-  if (variant == 1 && (c->dm.scheme == 1 || !dg::wave_stage_supported(c->dm.N, c->dm.precision)))
-    return fail(c, DG_EINVAL, "the wavefront-private stage kernel needs the FP32 form and N <= 4");
+  if (variant == 1 && (c->dm.scheme == 1 || !dg::spec_stage_supported(c->dm.N, c->dm.precision)))
+    return fail(c, DG_EINVAL, "the role-specialized stage kernel needs the nodal scheme, the FP32 form and N <= 4");
   c->dm.variant = variant;
   drop_graphs(c);
   return DG_OK;

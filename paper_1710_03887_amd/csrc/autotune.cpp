@@ -105,13 +105,13 @@ int dg_autotune(dg_ctx* c, const float* q, float* res, const char* cache_path, i
   }
   const std::string key = "single/N" + std::to_string(c->dm.N) + "/K" + std::to_string(c->dm.K) +
                           "/prec" + std::to_string(c->dm.precision) + "/" + device_key();
-  const bool wave_ok = dg::wave_stage_supported(c->dm.N, c->dm.precision) && !c->dm.sigma;
+  const bool wave_ok = dg::spec_stage_supported(c->dm.N, c->dm.precision);
   int best = 0, best_v = 0;
   if (!cache_lookup(cache_path, key, &best, &best_v) || best < 1 ||
       best > c->max_blocks_per_cu || best_v < 0 || best_v > 1 || (best_v == 1 && !wave_ok)) {
     double best_us = 1e300;
     // the tile-cooperative kernel at every residency, then the
-    // wavefront-private kernel (one block of eight wavefronts per CU)
+    // role-specialized kernel (one block of eight wavefronts per CU)
     const int ncand = c->max_blocks_per_cu + (wave_ok ? 1 : 0);
     for (int cand = 0; cand < ncand; ++cand) {
       const int variant = cand < c->max_blocks_per_cu ? 0 : 1;

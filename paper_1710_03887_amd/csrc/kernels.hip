@@ -834,6 +834,10 @@ size_t stage_lds_bytes(int N) {
 }
 
 hipError_t prepare_kernels(int N, int precision, int* blocks_per_cu) {
+  if (spec_stage_supported(N, precision)) {
+    const hipError_t e = prepare_spec_stage(N);
+    if (e != hipSuccess) return e;
+  }
   switch (N) {
     case 1: return stage_prepare<1>(precision, blocks_per_cu);
     case 2: return stage_prepare<2>(precision, blocks_per_cu);
@@ -847,8 +851,8 @@ hipError_t prepare_kernels(int N, int precision, int* blocks_per_cu) {
 hipError_t launch_stage(const DeviceMesh& m, int mode, const float* q_in, float* q_out, float* res,
                         float* out, float a, float b, double c, double t_host, double dt_host,
                         RunScalars* run, int rate_out, hipStream_t s) {
-  if (m.variant == 1 && wave_stage_supported(m.N, m.precision) && !m.sigma)
-    return launch_wave_stage(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run,
+  if (m.variant == 1 && spec_stage_supported(m.N, m.precision))
+    return launch_spec_stage(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run,
                              rate_out, s);
   switch (m.N) {
     case 1: return stage_dispatch<1>(m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out, s);

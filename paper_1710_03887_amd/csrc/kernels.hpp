@@ -30,7 +30,7 @@ struct DeviceMesh {
   const float* lghost = nullptr;
   // absorbing layer: damping rate per node [K][Np] (rhs -= sigma q'), or null
   const float* sigma = nullptr;
-  int variant = 0;                  // stage kernel: 0 tile-cooperative, 1 wavefront-private
+  int variant = 0;                  // stage kernel: 0 tile-cooperative, 1 role-specialized
   // 0: nodal strong form + LSERK4; 1: weak form with Gauss quadrature + RK2
   int scheme = 0;
   const float* qtab = nullptr;      // quadrature-scheme tables (scheme 1)
@@ -61,10 +61,12 @@ hipError_t launch_stage(const DeviceMesh& m, int mode, const float* q_in, float*
                         float* res, float* out, float a, float b, double c, double t_host,
                         double dt_host, RunScalars* run, int rate_out, hipStream_t s);
 
-// The wavefront-private stage kernel (same contract as launch_stage), for
-// the FP32 form at N <= 4.
-bool wave_stage_supported(int N, int precision);
-hipError_t launch_wave_stage(const DeviceMesh& m, int mode, const float* q_in, float* q_out,
+// The role-specialized stage kernel (same contract as launch_stage): four
+// surface and four contraction wavefronts per block, one block per CU; FP32
+// form at N <= 4.  prepare_spec_stage raises its dynamic-LDS limit.
+bool spec_stage_supported(int N, int precision);
+hipError_t prepare_spec_stage(int N);
+hipError_t launch_spec_stage(const DeviceMesh& m, int mode, const float* q_in, float* q_out,
                              float* res, float* out, float a, float b, double c, double t_host,
                              double dt_host, RunScalars* run, int rate_out, hipStream_t s);
 

@@ -2,7 +2,7 @@
 oracle, on a box whose x = 1 face is bent onto a spherical cap: one
 right-hand side (as for straight meshes: FP32 3e-6 relative L2 and 1e-5 node
 by node per element group, split-BF16 2e-4 and 1e-3), with an absorbing
-layer, with the wavefront-private stage kernel, 100 LSERK steps under the
+layer, with the role-specialized stage kernel, 100 LSERK steps under the
 CFL rule (1e-5 for p'), and the error paths."""
 import numpy as np
 import pytest

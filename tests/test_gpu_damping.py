@@ -1,8 +1,9 @@
 """The absorbing layer (dg_set_damping) against the FP64 oracle's
 rhs - sigma (q - q0), with the bars of the plain operator (one right-hand
 side: FP32 3e-6 relative L2 and 1e-5 node by node per element group,
-split-BF16 2e-4 and 1e-3; 1e-5 for p' after 100 steps).  A context set to the wavefront-private kernel runs the
-tile-cooperative one while a layer is set (checked through the same bars)."""
+split-BF16 2e-4 and 1e-3; 1e-5 for p' after 100 steps), with both stage
+kernels (variant 1: the role-specialized kernel, which applies the layer in
+its epilogue too)."""
 import numpy as np
 import pytest
 
