@@ -9,8 +9,8 @@ bell and near the outer boundary (Table 2 gives each sensor's distance from
 the bell and from the boundary): matching spectra mean the boundary
 treatment let the pulse out without disturbing the solution.  Here the
 domains are the synthetic trumpet domains of this package (Type A: box,
-sphere of radius 1.5, cone; Type B: half box, half cone), the sensors
-stand-ins placed by their relation to
+sphere of radius 1.5, cone, spherical cone; Type B: half box, half cone),
+the sensors stand-ins placed by their relation to
 the bell plane (x = 1): three at the same place in every domain, and on the
 axis a pair 2 cm and 1 cm before each domain's own far wall, and every
 signal is recorded every step by the library's probe kernel inside the
@@ -18,6 +18,14 @@ captured step graph, with one fixed time step shared by all domains so that
 the spectra share their frequency bins.
 
     python -m paper_1710_03887_amd.sensors [--amps 0.005,0.02] [--t-end 3.0] [--curved]
+    python -m paper_1710_03887_amd.sensors --quadrature --N 1 --amps 0.005,0.02,0.1
+
+With --quadrature the runs use the paper's own discretization (weak form with
+Gauss quadrature, RK2; DG_SETUP_QUADRATURE), which carries the 10% pulse that
+the unlimited nodal scheme does not; the summary then also compares each
+amplitude's spectra, rescaled by the amplitude ratio, with the smallest
+amplitude's (a linear response gives 0 dB: growth there is the pulse's own
+nonlinearity plus whatever the boundary sends back).
 
 With --curved the study compares the spherical domain with flat side faces
 against the same mesh with its side faces laid onto the sphere (curved
@@ -45,14 +53,18 @@ HZ = 343.0            # one time unit is 1/343 s (lengths in metres, c0 = 1)
 P_REF = 2e-5 / 101325.0 * P0
 # sensors at the same place in every domain ...
 SENSORS = {
-    "sensor 1 (1 cm before the bell edge, y = 0.99)": (1.01, 0.99, 0.003),
+    # 1 cm in front of the bell plane and 1 cm below the box's top wall (as
+    # Table 2 places it); in the other domains it is farther from their
+    # boundaries, so differences there against the box include the box's
+    # own behaviour next to its wall
+    "sensor 1 (1 cm in front of the bell plane, 1 cm below the box's top wall)": (1.01, 0.99, 0.003),
     "sensor 4 (in front of the bell, 0.57 up)": (1.29, 0.57, 0.003),
     "bore (1 cm inside the mouthpiece)": (0.01, 0.0, 0.003),
 }
 # ... and, per domain, on the axis 2 cm and 1 cm before its own far wall
 FAR = ("sensor 2 (on axis, 2 cm before the far wall)", "sensor 3 (on axis, 1 cm before the far wall)")
-DOMAINS = (("box", 50_000), ("sphere", 80_000), ("cone", 80_000), ("half", 30_000),
-           ("half-cone", 40_000))
+DOMAINS = (("box", 50_000), ("sphere", 80_000), ("cone", 80_000), ("scone", 80_000),
+           ("half", 30_000), ("half-cone", 40_000))
 
 
 def _torch():
@@ -96,14 +108,15 @@ def sensor_points(m, side=False):
     return pts
 
 
-def setup(kind, target_K, amp, N=4, side=False):
-    """kind: 'box', 'sphere', 'half', or 'sphere-curved' (the spherical domain
-    with its side faces laid onto the sphere as curved elements)."""
+def setup(kind, target_K, amp, N=4, side=False, quadrature=False):
+    """kind: one of the trumpet_domain kinds, or 'sphere-curved' (the
+    spherical domain with its side faces laid onto the sphere as curved
+    elements)."""
     from workloads import trumpet_domain
     torch = _torch()
     m = trumpet_domain(kind.replace("-curved", ""), target_K)
     ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, gamma=GAMMA, rho0=RHO0, p0=P0,
-                           inflow_amp=amp * P0, inflow_alpha=ALPHA)
+                           inflow_amp=amp * P0, inflow_alpha=ALPHA, quadrature=quadrature)
     q = torch.zeros((ctx.K, 5, ctx.Np), dtype=torch.float32, device="cuda")
     res = torch.zeros_like(q)
     if kind.endswith("-curved"):
@@ -146,22 +159,37 @@ def main():
     ap.add_argument("--N", type=int, default=4)
     ap.add_argument("--curved", action="store_true",
                     help="compare the spherical domain with flat and with curved side faces")
+    ap.add_argument("--quadrature", action="store_true",
+                    help="the paper's discretization (Gauss quadrature, RK2) instead of the nodal one")
+    ap.add_argument("--cfl", type=float, default=None,
+                    help="CFL of the shared fixed step (default 0.5 nodal, 0.3 quadrature)")
     args = ap.parse_args()
+    cfl = args.cfl if args.cfl is not None else (0.3 if args.quadrature else 0.5)
     torch = _torch()
     names = list(SENSORS) + list(FAR) + (list(SIDE) if args.curved else [])
     domains = (("sphere", 80_000), ("sphere-curved", 80_000)) if args.curved else DOMAINS
     ref_kind = domains[0][0]
-    summary = {"sensors": SENSORS, "runs": []}
+    summary = {"sensors": SENSORS, "runs": [], "scheme": "quadrature-RK2" if args.quadrature
+               else "nodal-LSERK4", "N": args.N}
+    all_db = {}
     for amp in [float(a) for a in args.amps.split(",") if a]:
-        ctxs = {kind: setup(kind, K, amp, args.N, args.curved) for kind, K in domains}
-        dt = 0.9 * min(dg.dg_stable_dt(c, q, 0.5) for c, q, _, _ in ctxs.values())
+        ctxs = {kind: setup(kind, K, amp, args.N, args.curved, args.quadrature)
+                for kind, K in domains}
+        dt = 0.9 * min(dg.dg_stable_dt(c, q, cfl) for c, q, _, _ in ctxs.values())
         nsteps = int(math.ceil(args.t_end / dt))
         freqs = np.arange(nsteps // 2 + 1) / (nsteps * dt) * HZ
         octaves = [f for f in (125, 250, 500, 1000, 2000, 4000, 8000) if f < freqs[-1]]
         bins = [int(np.argmin(np.abs(freqs - f))) for f in octaves]
         db, peak = {}, {}
         for kind, (ctx, q, res, pts) in ctxs.items():
-            s, t, secs = record(ctx, q, res, nsteps, dt, len(names), label=f"{kind} {amp}")
+            try:
+                s, t, secs = record(ctx, q, res, nsteps, dt, len(names), label=f"{kind} {amp}")
+            except dg.DGError as err:   # a non-physical state: reported, domain left out
+                print(json.dumps({"amp": amp, "domain": kind, "failed": str(err),
+                                  "first_bad_step": dg.dg_last_step(ctx)}), flush=True)
+                summary.setdefault("failed", []).append({"amp": amp, "domain": kind})
+                dg.dg_destroy(ctx)
+                continue
             db[kind] = spectra(s)
             peak[kind] = s.abs().max(dim=0).values.double().cpu().numpy()
             row = {"amp": amp, "domain": kind, "K": ctx.K, "steps": nsteps, "dt": dt, "t_end": t,
@@ -175,6 +203,9 @@ def main():
             dg.dg_destroy(ctx)
             del q, res
             torch.cuda.empty_cache()
+        all_db[amp] = db
+        if ref_kind not in db:
+            continue
         ref = db[ref_kind]
         for kind in db:
             if kind == ref_kind:
@@ -195,6 +226,26 @@ def main():
                 band = (db[kind][i2] > db[kind][i2].max() - 60) & (freqs > 300) & (freqs < 4000)
                 summary.setdefault(key, {}).setdefault(str(amp), {})[kind] = \
                     float(np.mean(db[kind][i3, band] - db[kind][i2, band])) if band.any() else None
+    # amplitude scaling: each amplitude's spectra lowered by 20 log10(amp / the
+    # smallest amp) against the smallest amplitude's, over its band
+    amps = sorted(all_db)
+    if len(amps) > 1:
+        a0 = amps[0]
+        for amp in amps[1:]:
+            shift = 20.0 * np.log10(amp / a0)
+            for kind in all_db[amp]:
+                if kind not in all_db[a0]:
+                    continue
+                d0, d1 = all_db[a0][kind], all_db[amp][kind]
+                n = min(d0.shape[1], d1.shape[1])
+                vals = {}
+                for i, nm in enumerate(names):
+                    band = (d0[i, :n] > d0[i, :n].max() - 60)
+                    band[:2] = False
+                    vals[nm] = float(np.mean(np.abs(d1[i, :n][band] - shift - d0[i, :n][band]))) \
+                        if band.any() else None
+                summary.setdefault("mean_abs_db_vs_smallest_amp_rescaled", {}) \
+                    .setdefault(str(amp), {})[kind] = vals
     print(json.dumps({k: v for k, v in summary.items() if k != "runs"}), flush=True)
 
 

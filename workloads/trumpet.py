@@ -18,14 +18,24 @@ three tetrahedra with every side-face diagonal running from the bottom
 vertex of lower cross-section id to the top vertex of higher id; the choice
 depends only on the shared edge, so the tetrahedral mesh is conforming.
 
-Outer domains: 'box' [-0.5, 1.8] x [-1, 1]^2; 'sphere' of radius 1.5 about
-(0.5, 0, 0), cut by the planes where its cross-section becomes narrower than
-the grid needs (flat caps); 'cone': x in [-0.5, 1.8] inside the cone of
-half-angle 30 degrees about the x axis with its apex at x = -1.3 (radius 0.46
-at the back cap, 1.79 at the front cap); 'half': the bore plus the box region
-x >= 1 in front of the bell (the region behind the bell is left out);
-'half-cone': the bore plus the cone region x >= 1.  `scale` grows
-the outer domain linearly about (0.65, 0, 0) with the instrument fixed.
+Outer domains (Type A: the whole instrument inside; Type B: the bore plus
+only the region x >= 1 in front of the bell, Section 3):
+  'box'       [-0.5, 1.8] x [-1, 1]^2;
+  'sphere'    radius 1.5 about (0.5, 0, 0), cut by the planes where its
+              cross-section becomes narrower than the grid needs (flat caps);
+  'cone'      x in [-0.5, 1.8] inside the cone of half-angle 30 degrees about
+              the x axis with its apex at x = -1.3 (radius 0.46 at the back
+              cap, 1.79 at the front cap);
+  'scone'     the same cone closed in front by the sphere about its apex
+              through (1.8, 0, 0) instead of a flat cap (a spherical cone; flat
+              cap where the sphere becomes too narrow for the grid, x ~ 1.65);
+  'half'      Type B: the box region in front of the bell;
+  'half-cone' Type B: the cone of half-angle 45 degrees whose base is the bell
+              plane x = 1 (radius 1.02 there) and whose apex is on the axis at
+              x = 2.02, cut by a flat cap where its radius falls to 0.15
+              (x = 1.87): its side meets the outgoing pulse at about 45 degrees.
+`scale` grows the box-like outer domains linearly about (0.65, 0, 0) with the
+instrument fixed.
 """
 import numpy as np
 
@@ -37,12 +47,25 @@ MOUTH_R = 0.4
 KAPPA = np.log(MOUTH_R / BORE_R) / (BELL_X1 - BELL_X0)
 CENTER_X = 0.65
 CONE_APEX_X, CONE_SLOPE = -1.3, float(np.tan(np.pi / 6))
+# Type B half cone: converging at 45 degrees from the bell plane to an apex on
+# the axis; the mesh stops at a flat cap of radius HALF_CONE_CAP_R
+HALF_CONE_APEX_X, HALF_CONE_CAP_R = 2.02, 0.15
 
 
 def instrument_radius(x):
     x = np.asarray(x, dtype=np.float64)
     return np.where(x <= BELL_X0, BORE_R,
                     BORE_R * np.exp(KAPPA * (np.minimum(x, BELL_X1) - BELL_X0)))
+
+
+def _outer_radius(x, cone):
+    """Radius of a conical outer boundary at x: slope (x - apex), closed by the
+    sphere of radius sphere_r about the apex when one is given."""
+    x = np.asarray(x, dtype=np.float64)
+    r = cone["slope"] * (x - cone["apex"])
+    if cone["sphere_r"] is not None:
+        r = np.minimum(r, np.sqrt(np.maximum(cone["sphere_r"] ** 2 - (x - cone["apex"]) ** 2, 0.0)))
+    return r
 
 
 def _contour_radius(x, x_lo, x_hi):
@@ -139,8 +162,8 @@ def trumpet_domain(kind="box", target_K=200_000, scale=1.0, wall_tag=BC_WALL,
     Returns {'xyz', 'EToV', 'bc'} (see meshes.py) and, with return_info,
     an 'info' dict with the grid sizes and the wall/inflow geometry.
     """
-    if kind not in ("box", "sphere", "half", "cone", "half-cone"):
-        raise ValueError("kind must be 'box', 'sphere', 'half', 'cone' or 'half-cone'")
+    if kind not in ("box", "sphere", "half", "cone", "scone", "half-cone"):
+        raise ValueError("kind must be 'box', 'sphere', 'half', 'cone', 'scone' or 'half-cone'")
     halfk = kind in ("half", "half-cone")
     if kind == "sphere":
         x_lo, x_hi, half_w = 0.5 - 1.5, 0.5 + 1.5, 1.5
@@ -150,7 +173,14 @@ def trumpet_domain(kind="box", target_K=200_000, scale=1.0, wall_tag=BC_WALL,
     x_hi = CENTER_X + (x_hi - CENTER_X) * scale
     half_w *= scale
     sph_c, sph_r = np.array([0.5, 0.0, 0.0]), 1.5 * scale
-    cone = (CENTER_X + (CONE_APEX_X - CENTER_X) * scale, CONE_SLOPE) if kind.endswith("cone") else None
+    cone = None
+    if kind in ("cone", "scone"):
+        apex = CENTER_X + (CONE_APEX_X - CENTER_X) * scale
+        cone = {"apex": apex, "slope": CONE_SLOPE,
+                "sphere_r": (x_hi - apex) if kind == "scone" else None}
+    elif kind == "half-cone":
+        x_hi = HALF_CONE_APEX_X - HALF_CONE_CAP_R
+        cone = {"apex": HALF_CONE_APEX_X, "slope": -1.0, "sphere_r": None}
 
     def layout(s):
         nt = max(2, int(round(6 * s)))
@@ -167,6 +197,9 @@ def trumpet_domain(kind="box", target_K=200_000, scale=1.0, wall_tag=BC_WALL,
             _graded(BELL_X1, x_hi, nfront, 4.0 * scale)]))
         if kind == "sphere":
             xs = _sphere_planes(xs, x_lo, x_hi, sph_c, sph_r)
+        if kind == "scone":
+            keep = _outer_radius(xs, cone) > 1.6 * _contour_radius(xs, x_lo, x_hi)
+            xs = xs[keep]
         return nt, nr1, nr2, xs
 
     def count(s):
@@ -219,7 +252,9 @@ def _assemble(kind, nt, nr1, nr2, xs, x_lo, x_hi, half_w, sph_c, sph_r, wall_tag
         if kind == "sphere":
             outer_r = np.sqrt(max(sph_r ** 2 - (x - sph_c[0]) ** 2, 0.0))
         elif cone is not None:
-            outer_r = cone[1] * (x - cone[0])
+            outer_r = float(_outer_radius(x, cone))
+            if x > BELL_X1 + 1e-12:   # in front of the bell the grid circle is only a
+                R = min(R, 0.5 * outer_r)  # grid line: it follows a converging outer wall
         for n, key in enumerate(desc):
             if key[0] == "in":
                 u = -1.0 + 2.0 * key[1] / nt
