@@ -467,8 +467,13 @@ int dg_set_curved(dg_ctx* ctx, const double* xyz_nodes, double tol, int64_t* n_c
  * its interpolation weights w (value at the point = sum_i w[i] u[node i], in
  * the library's node order); either may be NULL.  On a host-only context
  * the points are located and weighed but no probe set is kept.
- * In an element of the curved set (dg_set_curved, set before) the point's
- * reference coordinates come from inverting that element's curved map.
+ * With a curved set (dg_set_curved, set before), a point whose straight-sided
+ * element is curved, or that lies outside the straight-sided mesh, is
+ * located by inverting the maps of the curved elements near it: it belongs
+ * to the one whose reference point has the largest smallest barycentric
+ * coordinate, which must be >= -1e-9 (so a point between a chord and a face
+ * bent outward is found, and one beyond a curved face that moved into its
+ * straight-sided element goes to the neighbour whose curved image holds it).
  * Synchronous.  Errors: DG_EINVAL for n outside 1..2^20, a point outside
  * the mesh (tolerance 1e-9 in barycentric coordinates) or a curved map that
  * does not invert, DG_ENOMEM. */

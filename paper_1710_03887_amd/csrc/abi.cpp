@@ -671,15 +671,16 @@ int dg_probe_setup(dg_ctx* c, const double* xyz, int32_t n, int64_t* elements_ou
   std::vector<double> wd(Np);
   for (int32_t p = 0; p < n; ++p) {
     double rst[3];
-    elem[p] = dg::locate_point(c->mesh, xyz + size_t(p) * 3, 1e-9, rst);
+    // with a curved set, a point whose straight-sided element is curved (or
+    // that lies outside the straight-sided mesh) is located by inverting the
+    // maps of the curved elements near it
+    elem[p] = c->curved_elem_host.empty()
+                  ? dg::locate_point(c->mesh, xyz + size_t(p) * 3, 1e-9, rst)
+                  : dg::locate_point_curved(c->ops, c->mesh, c->curved_elem_host,
+                                            c->curved_x_host.data(), xyz + size_t(p) * 3, 1e-9, rst);
+    if (elem[p] == -2)
+      return fail(c, DG_EINVAL, "probe " + std::to_string(p) + ": its curved element's map did not invert");
     if (elem[p] < 0) return fail(c, DG_EINVAL, "probe " + std::to_string(p) + " lies outside the mesh");
-    // in a curved element: invert its curved map, from the straight-sided estimate
-    const auto it = std::lower_bound(c->curved_elem_host.begin(), c->curved_elem_host.end(), elem[p]);
-    if (it != c->curved_elem_host.end() && *it == elem[p]) {
-      const size_t ci = size_t(it - c->curved_elem_host.begin());
-      if (!dg::invert_element_map(c->ops, c->curved_x_host.data() + ci * Np * 3, xyz + size_t(p) * 3, rst))
-        return fail(c, DG_EINVAL, "probe " + std::to_string(p) + ": its curved element's map did not invert");
-    }
     dg::interpolation_weights(c->ops, rst, wd.data());
     for (int i = 0; i < Np; ++i) w[size_t(p) * Np + i] = float(wd[i]);
     if (weights_out) std::copy(wd.begin(), wd.end(), weights_out + size_t(p) * Np);

@@ -656,25 +656,83 @@ std::string curved_geometry(const RefOps& ops, const HostMesh& m, const double* 
   return "";
 }
 
+namespace {
+
+// Smallest barycentric coordinate of x in element k's straight-sided image,
+// and x's reference coordinates there.
+double straight_min_barycentric(const HostMesh& m, int64_t k, const double x[3], double rst[3]) {
+  const double* X = &m.xyz[size_t(k) * 12];
+  const double* G = &m.drst_dx[size_t(k) * 9];
+  const double d[3] = {x[0] - X[0], x[1] - X[1], x[2] - X[2]};
+  // x - v0 = sum_a (1 + r_a)/2 (v_a - v0): (1 + r_a) = G[a] . (x - v0)
+  double l[4];
+  for (int a = 0; a < 3; ++a) l[a + 1] = 0.5 * (G[a * 3] * d[0] + G[a * 3 + 1] * d[1] + G[a * 3 + 2] * d[2]);
+  l[0] = 1.0 - l[1] - l[2] - l[3];
+  for (int a = 0; a < 3; ++a) rst[a] = 2.0 * l[a + 1] - 1.0;
+  return std::min(std::min(l[0], l[1]), std::min(l[2], l[3]));
+}
+
+// Smallest barycentric coordinate of the reference point rst.
+double ref_min_barycentric(const double rst[3]) {
+  const double l0 = -0.5 * (1.0 + rst[0] + rst[1] + rst[2]);
+  return std::min(std::min(l0, 0.5 * (1.0 + rst[0])),
+                  std::min(0.5 * (1.0 + rst[1]), 0.5 * (1.0 + rst[2])));
+}
+
+}  // namespace
+
 int64_t locate_point(const HostMesh& m, const double x[3], double tol, double rst[3]) {
   int64_t best = -1;
   double best_min = -1e300;
   for (int64_t k = 0; k < m.K; ++k) {
-    const double* X = &m.xyz[size_t(k) * 12];
-    const double* G = &m.drst_dx[size_t(k) * 9];
-    const double d[3] = {x[0] - X[0], x[1] - X[1], x[2] - X[2]};
-    // x - v0 = sum_a (1 + r_a)/2 (v_a - v0): (1 + r_a) = G[a] . (x - v0)
-    double l[4];
-    for (int a = 0; a < 3; ++a) l[a + 1] = 0.5 * (G[a * 3] * d[0] + G[a * 3 + 1] * d[1] + G[a * 3 + 2] * d[2]);
-    l[0] = 1.0 - l[1] - l[2] - l[3];
-    const double mn = std::min(std::min(l[0], l[1]), std::min(l[2], l[3]));
+    double r[3];
+    const double mn = straight_min_barycentric(m, k, x, r);
     if (mn > best_min) {
       best_min = mn;
       best = k;
-      for (int a = 0; a < 3; ++a) rst[a] = 2.0 * l[a + 1] - 1.0;
+      for (int a = 0; a < 3; ++a) rst[a] = r[a];
     }
   }
   return best_min >= -tol ? best : -1;
+}
+
+int64_t locate_point_curved(const RefOps& ops, const HostMesh& m,
+                            const std::vector<int64_t>& curved, const double* xc,
+                            const double x[3], double tol, double rst[3]) {
+  const int64_t k = locate_point(m, x, tol, rst);
+  if (k >= 0 && !std::binary_search(curved.begin(), curved.end(), k)) return k;
+  // candidates: curved elements whose straight-sided image is near x, nearest first
+  std::vector<std::pair<double, size_t>> near;
+  for (size_t i = 0; i < curved.size(); ++i) {
+    double r[3];
+    const double mn = straight_min_barycentric(m, curved[i], x, r);
+    if (mn >= -0.5) near.emplace_back(-mn, i);
+  }
+  std::stable_sort(near.begin(), near.end(),
+                   [](const std::pair<double, size_t>& a, const std::pair<double, size_t>& b) {
+                     return a.first < b.first;
+                   });
+  const int Np = ops.Np;
+  int64_t best = -1;
+  double best_min = -1e300;
+  bool own_failed = false;
+  for (const auto& c : near) {
+    const int64_t kc = curved[c.second];
+    double r[3];
+    (void)straight_min_barycentric(m, kc, x, r);
+    if (!invert_element_map(ops, xc + c.second * size_t(Np) * 3, x, r)) {
+      own_failed = own_failed || kc == k;
+      continue;
+    }
+    const double mn = ref_min_barycentric(r);
+    if (mn > best_min) {
+      best_min = mn;
+      best = kc;
+      for (int a = 0; a < 3; ++a) rst[a] = r[a];
+    }
+  }
+  if (best >= 0 && best_min >= -tol) return best;
+  return own_failed ? -2 : -1;
 }
 
 void interpolation_weights(const RefOps& ops, const double rst[3], double* w) {

@@ -99,6 +99,21 @@ int64_t locate_point(const HostMesh& mesh, const double x[3], double tol, double
 // place).  Returns false when it does not converge (|step| <= 1e-13 within
 // 50 iterations) or meets a singular Jacobian.
 bool invert_element_map(const RefOps& ops, const double* xe, const double x[3], double rst[3]);
+// Element containing x when some elements are curved (curved: their ids,
+// ascending; xc: their node positions [n][Np][3] in that order).  A point
+// whose straight-sided element is straight is located as by locate_point.
+// Otherwise the curved elements whose straight-sided images lie near x
+// (smallest barycentric coordinate >= -0.5) have their maps inverted, nearest
+// first, and the one whose reference point has the largest smallest
+// barycentric coordinate is taken if that coordinate is >= -tol: a point
+// between a chord and a face bent outward, or beyond a curved face that moved
+// into its straight-sided element, lands in the element whose curved image
+// holds it.  Returns the element, -1 when no element holds the point, or -2
+// when the point lies in a curved element's straight-sided image and no map
+// that could hold it inverts.
+int64_t locate_point_curved(const RefOps& ops, const HostMesh& mesh,
+                            const std::vector<int64_t>& curved, const double* xc,
+                            const double x[3], double tol, double rst[3]);
 // Nodal interpolation weights w[i] = l_i(r, s, t) of the order-N nodal basis
 // at a reference point: the polynomial through nodal values u_i takes the
 // value sum_i w[i] u_i there.
