@@ -169,6 +169,9 @@ int dg_geometry(const dg_ctx* ctx, double* drst_dx, double* J, double* nrm,
  * + sum_f Fscale_f LIFT_f dF_f at time t (t enters through inflow faces).
  * q, rhs: device FP32 [K][5][Np] perturbation states (see conventions).
  * Asynchronous on stream; no allocation.
+ * Interface note: q holds q' = q - q0, not the conserved q (and so do the
+ * states of dg_step, dg_stage, dg_run and the batch): acoustic perturbations
+ * of 1e-3 p0 and below keep their digits in FP32.
  */
 int dg_rhs(dg_ctx* ctx, const float* q, float* rhs, double t, void* stream);
 
@@ -298,7 +301,9 @@ int dg_get_kernel(const dg_ctx* ctx);
  * architecture and CU count; a cached entry is applied without timing.
  * Results of the solver do not depend on the launch shape.
  * q is read and left unchanged; res is overwritten (scratch).  The chosen
- * shape is returned through the optional out pointers.  Synchronizes. */
+ * shape is returned through the optional out pointers.  Synchronizes.
+ * Interface note: it times on a caller-given state and scratch buffer and
+ * keeps a plain-text cache (not JSON), so that no hidden allocation occurs. */
 int dg_autotune(dg_ctx* ctx, const float* q, float* res, const char* cache_path,
                 int* blocks_per_cu, void* stream);
 
@@ -326,7 +331,9 @@ int dg_batch_autotune(dg_batch* b, float* const* q, float* const* res, const cha
 #define DG_MLP_PARAMS 36299
 typedef struct dg_mlp dg_mlp;
 
-/* params: host FP32 [DG_MLP_PARAMS], copied.  Synchronizes. */
+/* params: host FP32 [DG_MLP_PARAMS], copied.  Synchronizes.
+ * Interface note: there is no seed argument; the library draws no random
+ * numbers, so the initial weights always come from the caller. */
 int dg_mlp_create(const float* params, void* stream, dg_mlp** out);
 int dg_mlp_destroy(dg_mlp* m);
 const char* dg_mlp_last_error(const dg_mlp* m);
@@ -379,7 +386,9 @@ int dg_mlp_train_step(dg_mlp* m, const float* X, const float* Y, int64_t n_rows,
  * the ghost is  char + blend * (network - char)  (blend in [0, 1]; 1 = the
  * network alone), elsewhere the characteristic ghost.  The network is
  * borrowed and must outlive the attachment; weight updates take effect at the
- * next launch. */
+ * next launch.
+ * Interface note: besides the amplitude window (p_lo, p_hi) it takes the
+ * input normalization and the blend weight. */
 int dg_set_learned_bc(dg_ctx* ctx, dg_mlp* m, double norm, double p_lo, double p_hi,
                       double blend);
 
@@ -394,7 +403,9 @@ int64_t dg_learned_faces(const dg_ctx* ctx, int64_t* faces);
  * |q - q0| of the face's characteristic ghost): the
  * neighbour's trace on interior faces (a larger domain's solution), the ghost
  * of the face's tag on boundary faces.  Face indices outside the mesh are
- * skipped.  Asynchronous. */
+ * skipped.  Asynchronous.
+ * Interface note: the extra norm argument selects the same normalization as
+ * dg_set_learned_bc, so sampled rows match what the solver feeds the network. */
 int dg_sample_traces(dg_ctx* ctx, const float* q, const int64_t* faces, int64_t nf, double norm,
                      float* X, float* Y, void* stream);
 

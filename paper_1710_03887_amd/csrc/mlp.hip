@@ -211,7 +211,6 @@ constexpr int kWaveBytes = 16 * kS1 * 2 + 2 * 16 * kS2 * 2;
 constexpr int kWeightBytes = kBfTotal * 2;
 constexpr int kInferLds = kWeightBytes + 4 * kWaveBytes;
 static_assert(16 * 80 * 4 <= 16 * kS1 * 2 + 16 * kS2 * 2, "output tile must fit over sX, sH1");
-static_assert(16 * kMlpOut * 4 <= 2 * 16 * kS2 * 2, "input staging must fit over sH1, sH2");
 
 __device__ __forceinline__ void load_weights(const uint16_t* Wb, uint16_t* sW) {
   const uint4* src = reinterpret_cast<const uint4*>(Wb);
@@ -309,46 +308,88 @@ __global__ __launch_bounds__(256) void infer_kernel(const uint16_t* Wb, const fl
 // ---- learned ghost traces (N = 4) -------------------------------------------
 
 constexpr int kNp4 = 35, kNfp4 = 15;
+constexpr int kGhostFaces = 16;  // faces per block: the N side of one MFMA tile
 
+// A operand of a weight tile: rows row0 + e, k-block kb (BF16, padded layout)
+__device__ __forceinline__ bf16x8 wfrag(const uint16_t* W, int row, int stride, int kb, int q4) {
+  return *reinterpret_cast<const bf16x8*>(W + row * stride + kb * 32 + 8 * q4);
+}
+
+// One block of four wavefronts per 16 learned faces.  Thread t < 240 owns
+// node t % 15 of face t / 15 from the gather to the store and keeps its
+// characteristic ghost in registers; the network's output rows are split
+// over the wavefronts (wavefront w: hidden tiles 2w, 2w+1 of layers 1 and 2,
+// output tiles w and, for w = 0, 4 of layer 3), whose weights each
+// wavefront loads from global memory straight into registers at entry, so
+// the weights are read once per block and never staged in LDS.
 __global__ __launch_bounds__(256) void learned_ghost_kernel(DeviceMesh m, LearnedBC L,
                                                             const float* q) {
-  extern __shared__ uint4 smem4[];
-  uint16_t* smem = reinterpret_cast<uint16_t*>(smem4);
-  __shared__ float sPmax[4][16];
-  __shared__ float sScale[4][16];
-  __shared__ unsigned sBad[4][16];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __bf16* sW = reinterpret_cast<__bf16*>(smem);
-  char* wb = reinterpret_cast<char*>(smem) + kWeightBytes + w * kWaveBytes;
-  __bf16* sX = reinterpret_cast<__bf16*>(wb);
-  __bf16* sH1 = sX + 16 * kS1;
-  __bf16* sH2 = sH1 + 16 * kS2;
-  float* sY = reinterpret_cast<float*>(wb);
+  __shared__ __attribute__((aligned(16))) __bf16 sX[kGhostFaces * kS1];
+  __shared__ __attribute__((aligned(16))) __bf16 sH1[kGhostFaces * kS2];
+  __shared__ __attribute__((aligned(16))) __bf16 sH2[kGhostFaces * kS2];
+  // the characteristic ghost [16][75] until the inputs are built, then the
+  // network's FP32 outputs [16][80]
+  __shared__ float sY[kGhostFaces * 80];
+  __shared__ float sNrm[kGhostFaces][3];
+  __shared__ float sPmax[kGhostFaces], sScale[kGhostFaces];
+  __shared__ unsigned sBad[kGhostFaces];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, e = lane & 15, q4 = lane >> 4;
   const Phys& P = m.phys;
-  load_weights(L.Wb, smem);
-  if (lane < 16) {
-    sPmax[w][lane] = 0.0f;
-    sScale[w][lane] = 0.0f;
-    sBad[w][lane] = 0u;
+  const int64_t j0 = int64_t(blockIdx.x) * kGhostFaces;
+
+  // this wavefront's weight and bias fragments (uniform branch on w for the
+  // fifth output tile)
+  const bool tile4 = w == 0;
+  bf16x8 a1[2][3], a2[2][4], a3[2][4];
+  float b1[2][4], b2[2][4], b3[2][4];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int h = (2 * w + u) * 16;
+#pragma unroll
+    for (int kb = 0; kb < 3; ++kb) a1[u][kb] = wfrag(L.Wb + kBfW1, h + e, kS1, kb, q4);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) a2[u][kb] = wfrag(L.Wb + kBfW2, h + e, kS2, kb, q4);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      b1[u][r] = L.P[kOB1 + h + 4 * q4 + r];
+      b2[u][r] = L.P[kOB2 + h + 4 * q4 + r];
+    }
   }
-  const int64_t j0 = (int64_t(blockIdx.x) * 4 + w) * 16;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int o = (u == 0 ? w : 4) * 16;
+    if (u == 0 || tile4) {
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) a3[u][kb] = wfrag(L.Wb + kBfW3, o + e, kS2, kb, q4);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jj = o + 4 * q4 + r;
+        b3[u][r] = jj < kMlpOut ? L.P[kOB3 + jj] : 0.0f;
+      }
+    }
+  }
+
+  if (t < kGhostFaces) {
+    sPmax[t] = 0.0f;
+    sScale[t] = 0.0f;
+    sBad[t] = 0u;
+  }
   __syncthreads();
-  // per node: max |p'| of each face's interior trace, and the characteristic
-  // ghost (the network's input: the interior trace with its incoming
-  // acoustic characteristic removed), staged as FP32 over sH1/sH2; for
-  // per-face scaling, the ghost's largest |q'| over variables and nodes
-  float* sStage = reinterpret_cast<float*>(sH1);
-  for (int i = lane; i < 16 * kNfp4; i += 64) {
-    const int row = i / kNfp4, ii = i % kNfp4;
-    const int64_t j = j0 + row;
-    if (j >= L.nl) continue;
+  // per owned node: the characteristic ghost (the network's input: the
+  // interior trace with its incoming acoustic characteristic removed); per
+  // face: max |p'| of the interior trace and the ghost's largest |q'|
+  const int row = t / kNfp4, ii = t % kNfp4;
+  const int64_t j = j0 + row;
+  const bool own = t < kGhostFaces * kNfp4 && j < L.nl;
+  float qc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  if (own) {
     const int kf = L.lface[j];
     const int64_t k = kf >> 2;
     const int f = kf & 3;
     const int node = m.fmask[f * kNfp4 + ii];
     const float n[3] = {float(m.sgeo[k * 16 + f * 4 + 0]), float(m.sgeo[k * 16 + f * 4 + 1]),
                         float(m.sgeo[k * 16 + f * 4 + 2])};
-    float qm[5], qc[5], big = 0.0f;
+    float qm[5], big = 0.0f;
 #pragma unroll
     for (int v = 0; v < 5; ++v) qm[v] = q[(k * 5 + v) * kNp4 + node];
     Prim wm;
@@ -356,88 +397,91 @@ __global__ __launch_bounds__(256) void learned_ghost_kernel(DeviceMesh m, Learne
     ghost(P, BC_OUTFLOW_CHAR, qm, wm, n, 0.0f, qc);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      sStage[row * kMlpOut + v * kNfp4 + ii] = qc[v];
+      sY[row * kMlpOut + v * kNfp4 + ii] = qc[v];
       big = fmaxf(big, fabsf(qc[v]));
     }
-    atomicMax(reinterpret_cast<unsigned*>(&sPmax[w][row]), __float_as_uint(fabsf(wm.pp)));
-    atomicMax(reinterpret_cast<unsigned*>(&sScale[w][row]), __float_as_uint(big));
+    if (ii < 3) sNrm[row][ii] = n[ii];
+    atomicMax(reinterpret_cast<unsigned*>(&sPmax[row]), __float_as_uint(fabsf(wm.pp)));
+    atomicMax(reinterpret_cast<unsigned*>(&sScale[row]), __float_as_uint(big));
   }
   __syncthreads();
-  if (lane < 16 && L.norm > 0.0f) sScale[w][lane] = L.norm;
+  if (t < kGhostFaces && L.norm > 0.0f) sScale[t] = L.norm;
   __syncthreads();
   // inputs: characteristic ghost / scale (variable-major), then the normal
-  for (int i = lane; i < 16 * kS1; i += 64) {
-    const int row = i / kS1, c = i % kS1;
-    const int64_t j = j0 + row;
+  for (int i = t; i < kGhostFaces * kS1; i += 256) {
+    const int r = i / kS1, c = i % kS1;
     float v = 0.0f;
-    if (j < L.nl && c < kMlpIn) {
+    if (j0 + r < L.nl && c < kMlpIn) {
       if (c < 5 * kNfp4) {
-        const float sc = sScale[w][row];
-        v = sc > 0.0f ? sStage[row * kMlpOut + c] / sc : 0.0f;
+        const float sc = sScale[r];
+        v = sc > 0.0f ? sY[r * kMlpOut + c] / sc : 0.0f;
       } else {
-        const int kf = L.lface[j];
-        v = float(m.sgeo[(kf >> 2) * 16 + (kf & 3) * 4 + (c - 5 * kNfp4)]);
+        v = sNrm[r][c - 5 * kNfp4];
       }
     }
     sX[i] = to_bf16(v);
   }
   __syncthreads();
-  mlp_wave(sW, L.P, sX, sH1, sH2, sY);
-  // learned ghost = characteristic ghost + blend * (scale * network output -
-  // characteristic ghost); kept in sY, with a physical check at every node
-  for (int i = lane; i < 16 * kNfp4; i += 64) {
-    const int row = i / kNfp4, ii = i % kNfp4;
-    const int64_t j = j0 + row;
-    if (j >= L.nl) continue;
-    const int kf = L.lface[j];
-    const int64_t k = kf >> 2;
-    const int f = kf & 3;
-    const int node = m.fmask[f * kNfp4 + ii];
-    const float n[3] = {float(m.sgeo[k * 16 + f * 4 + 0]), float(m.sgeo[k * 16 + f * 4 + 1]),
-                        float(m.sgeo[k * 16 + f * 4 + 2])};
-    float qm[5], qg[5];
+  // layer 1: hidden tiles 2w, 2w+1
 #pragma unroll
-    for (int v = 0; v < 5; ++v) qm[v] = q[(k * 5 + v) * kNp4 + node];
-    Prim wm;
-    primitive<true>(P, qm, wm);
-    ghost(P, BC_OUTFLOW_CHAR, qm, wm, n, 0.0f, qg);
-    const float sc = sScale[w][row];
+  for (int u = 0; u < 2; ++u) {
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      qg[v] += L.blend * (sc * sY[row * 80 + v * kNfp4 + ii] - qg[v]);
-      sY[row * 80 + v * kNfp4 + ii] = qg[v];
+    for (int kb = 0; kb < 3; ++kb) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(sX + e * kS1 + kb * 32 + 8 * q4);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[u][kb], b, acc, 0, 0, 0);
     }
-    Prim wg;
-    primitive<true>(P, qg, wg);
-    if (!(wg.rho > 0.0f) || !(wg.p > 0.0f) || !(sc > 0.0f)) atomicOr(&sBad[w][row], 1u);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      sH1[e * kS2 + (2 * w + u) * 16 + 4 * q4 + r] = to_bf16(gelu(acc[r] + b1[u][r]));
   }
   __syncthreads();
-  for (int i = lane; i < 16 * kNfp4; i += 64) {
-    const int row = i / kNfp4, ii = i % kNfp4;
-    const int64_t j = j0 + row;
-    if (j >= L.nl) continue;
-    const float pm = sPmax[w][row];
-    const bool use = !sBad[w][row] && pm >= L.plo && pm <= L.phi;
-    float qg[5];
-    if (use) {
+  // layer 2
 #pragma unroll
-      for (int v = 0; v < 5; ++v) qg[v] = sY[row * 80 + v * kNfp4 + ii];
-    } else {
-      const int kf = L.lface[j];
-      const int64_t k = kf >> 2;
-      const int f = kf & 3;
-      const int node = m.fmask[f * kNfp4 + ii];
-      const float n[3] = {float(m.sgeo[k * 16 + f * 4 + 0]), float(m.sgeo[k * 16 + f * 4 + 1]),
-                          float(m.sgeo[k * 16 + f * 4 + 2])};
-      float qm[5];
+  for (int u = 0; u < 2; ++u) {
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int v = 0; v < 5; ++v) qm[v] = q[(k * 5 + v) * kNp4 + node];
-      Prim wm;
-      primitive<true>(P, qm, wm);
-      ghost(P, BC_OUTFLOW_CHAR, qm, wm, n, 0.0f, qg);
+    for (int kb = 0; kb < 4; ++kb) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(sH1 + e * kS2 + kb * 32 + 8 * q4);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[u][kb], b, acc, 0, 0, 0);
     }
 #pragma unroll
-    for (int v = 0; v < 5; ++v) L.ghost[(j * 5 + v) * kNp4 + ii] = qg[v];
+    for (int r = 0; r < 4; ++r)
+      sH2[e * kS2 + (2 * w + u) * 16 + 4 * q4 + r] = to_bf16(gelu(acc[r] + b2[u][r]));
+  }
+  __syncthreads();
+  // layer 3: output tiles w and (w = 0) 4, FP32 over sY
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    if (u == 1 && !tile4) break;
+    const int o = (u == 0 ? w : 4) * 16;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(sH2 + e * kS2 + kb * 32 + 8 * q4);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[u][kb], b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sY[e * 80 + o + 4 * q4 + r] = acc[r] + b3[u][r];
+  }
+  __syncthreads();
+  // learned ghost = characteristic ghost + blend * (scale * network output -
+  // characteristic ghost), with a physical check at every node
+  float qg[5];
+  if (own) {
+    const float sc = sScale[row];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) qg[v] = qc[v] + L.blend * (sc * sY[row * 80 + v * kNfp4 + ii] - qc[v]);
+    Prim wg;
+    primitive<true>(P, qg, wg);
+    if (!(wg.rho > 0.0f) || !(wg.p > 0.0f) || !(sc > 0.0f)) atomicOr(&sBad[row], 1u);
+  }
+  __syncthreads();
+  if (own) {
+    const float pm = sPmax[row];
+    const bool use = !sBad[row] && pm >= L.plo && pm <= L.phi;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) L.ghost[(j * 5 + v) * kNp4 + ii] = use ? qg[v] : qc[v];
   }
 }
 
@@ -582,9 +626,7 @@ hipError_t launch_learned_ghost(const DeviceMesh& m, const LearnedBC& L, const f
                                 hipStream_t s) {
   if (L.nl <= 0) return hipSuccess;
   if (m.N != 4) return hipErrorInvalidValue;
-  hipError_t e = lds_attr(reinterpret_cast<const void*>(&learned_ghost_kernel));
-  if (e != hipSuccess) return e;
-  learned_ghost_kernel<<<int((L.nl + 63) / 64), 256, kInferLds, s>>>(m, L, q);
+  learned_ghost_kernel<<<int((L.nl + kGhostFaces - 1) / kGhostFaces), 256, 0, s>>>(m, L, q);
   return hipGetLastError();
 }
 
