@@ -50,53 +50,100 @@ struct Gemm {
   const float* Z;
 };
 
+// Epilogue of output (mm, n) with the product sum v (n == N: the bias
+// gradient column of EP_WGRAD).
 template <int EP>
-__global__ __launch_bounds__(256) void gemm_kernel(Gemm g) {
+__device__ __forceinline__ void gemm_store(const Gemm& g, int mm, int n, float v) {
+  if (EP == EP_WGRAD) {
+    if (n < g.N) g.C[int64_t(mm) * g.ldc + n] = v;
+    else if (n == g.N) g.C2[mm] = v;
+    return;
+  }
+  if (n >= g.N) return;
+  const int64_t o = int64_t(mm) * g.ldc + n;
+  if (EP == EP_BIAS || EP == EP_BIAS_GELU) v += g.bias[n];
+  if (EP == EP_GELU_GRAD) v *= gelu_grad(g.Z[o]);
+  g.C[o] = v;
+  if (EP == EP_BIAS_GELU) g.C2[o] = gelu(v);
+}
+
+// One 16 x 16 output tile per block; the contraction range is split into
+// gridDim.z chunks (chunk z: k in [z kc, (z+1) kc)), and each chunk over the
+// four wavefronts (wavefront w: k-quads w, w+4, ...; 8 quads' loads issued
+// ahead of their products).  With one chunk the block applies the epilogue;
+// otherwise it writes its sum to part[z][mm][n] and gemm_finish_kernel adds
+// the chunks in order.  Every sum has a fixed order: results are bitwise
+// reproducible.
+template <int EP>
+__global__ __launch_bounds__(256) void gemm_kernel(Gemm g, int kc, float* part, int ldp) {
   __shared__ floatx4 red[4][64];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, e = lane & 15, q4 = lane >> 4;
   const int m0 = blockIdx.x * 16, n0 = blockIdx.y * 16;
   const int m = m0 + e, n = n0 + e;
+  const int kb = blockIdx.z * kc, ke = min(g.K, kb + kc);
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-  for (int k0 = 4 * w; k0 < g.K; k0 += 16) {
-    const int k = k0 + q4;
-    const bool kin = k < g.K;
-    const float a = (kin && m < g.M) ? g.A[int64_t(m) * g.sam + int64_t(k) * g.sak] : 0.0f;
-    float b = 0.0f;
-    if (kin) {
-      if (EP == EP_WGRAD && n == g.N) b = 1.0f;
-      else if (n < g.N) b = g.B[int64_t(k) * g.sbk + int64_t(n) * g.sbn];
+  for (int k00 = kb + 4 * w; k00 < ke; k00 += 16 * 8) {
+    float a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k00 + 16 * u + q4;
+      const bool kin = k < ke;
+      a[u] = (kin && m < g.M) ? g.A[int64_t(m) * g.sam + int64_t(k) * g.sak] : 0.0f;
+      b[u] = 0.0f;
+      if (kin) {
+        if (EP == EP_WGRAD && n == g.N) b[u] = 1.0f;
+        else if (n < g.N) b[u] = g.B[int64_t(k) * g.sbk + int64_t(n) * g.sbn];
+      }
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
   }
   red[w][lane] = acc;
   __syncthreads();
   if (w != 0) return;
-  const floatx4 s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  const floatx4 sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  const int ncol = EP == EP_WGRAD ? g.N + 1 : g.N;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int mm = m0 + 4 * q4 + r;
-    if (mm >= g.M) continue;
-    float v = s[r];
-    if (EP == EP_WGRAD) {
-      if (n < g.N) g.C[int64_t(mm) * g.ldc + n] = v;
-      else if (n == g.N) g.C2[mm] = v;
-      continue;
-    }
-    if (n >= g.N) continue;
-    const int64_t o = int64_t(mm) * g.ldc + n;
-    if (EP == EP_BIAS || EP == EP_BIAS_GELU) v += g.bias[n];
-    if (EP == EP_GELU_GRAD) v *= gelu_grad(g.Z[o]);
-    g.C[o] = v;
-    if (EP == EP_BIAS_GELU) g.C2[o] = gelu(v);
+    if (mm >= g.M || n >= ncol) continue;
+    if (gridDim.z == 1) gemm_store<EP>(g, mm, n, sum[r]);
+    else part[(int64_t(blockIdx.z) * g.M + mm) * ldp + n] = sum[r];
   }
 }
 
+// Adds the chunk sums part[0..kz)[mm][n] in order and applies the epilogue.
 template <int EP>
-hipError_t gemm(const Gemm& g, hipStream_t s) {
+__global__ __launch_bounds__(256) void gemm_finish_kernel(Gemm g, int kz, const float* part, int ldp) {
   const int ncol = EP == EP_WGRAD ? g.N + 1 : g.N;
-  dim3 grid((g.M + 15) / 16, (ncol + 15) / 16);
-  gemm_kernel<EP><<<grid, 256, 0, s>>>(g);
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(g.M) * ncol) return;
+  const int mm = int(i / ncol), n = int(i % ncol);
+  float v = 0.0f;
+  for (int z = 0; z < kz; ++z) v += part[(int64_t(z) * g.M + mm) * ldp + n];
+  gemm_store<EP>(g, mm, n, v);
+}
+
+// Contractions longer than kGemmSplitK are split into chunks of at least
+// that length, at most kGemmMaxChunks of them (partial sums in `part`,
+// kGemmMaxChunks x 128 x 129 floats).
+constexpr int kGemmSplitK = 512, kGemmMaxChunks = 8, kGemmPartLd = kMlpH + 1;
+static_assert(kMlpPartFloats >= int64_t(kGemmMaxChunks) * kMlpH * kGemmPartLd,
+              "chunk sums must fit the workspace");
+
+template <int EP>
+hipError_t gemm(const Gemm& g, hipStream_t s, float* part = nullptr) {
+  const int ncol = EP == EP_WGRAD ? g.N + 1 : g.N;
+  int kz = 1;
+  if (part && g.K > kGemmSplitK && g.M <= kMlpH && ncol <= kGemmPartLd)
+    kz = std::min(kGemmMaxChunks, (g.K + kGemmSplitK - 1) / kGemmSplitK);
+  const int kc = kz == 1 ? g.K : ((g.K + kz - 1) / kz + 15) / 16 * 16;
+  dim3 grid((g.M + 15) / 16, (ncol + 15) / 16, kz);
+  gemm_kernel<EP><<<grid, 256, 0, s>>>(g, kc, part, kGemmPartLd);
+  if (kz > 1) {
+    const int64_t n = int64_t(g.M) * ncol;
+    gemm_finish_kernel<EP><<<int((n + 255) / 256), 256, 0, s>>>(g, kz, part, kGemmPartLd);
+  }
   return hipGetLastError();
 }
 
@@ -571,21 +618,21 @@ hipError_t mlp_grad_f32(const float* P, const float* X, const float* Y, int64_t 
   // layer 3: dW3 = d3^T a2, db3 = sum d3; d2 = (d3 W3) * gelu'(z2)
   Gemm w3 = make(kMlpOut, kMlpH, b, w.d3, 1, kMlpOut, w.a2, kMlpH, 1, grads + kOW3, kMlpH);
   w3.C2 = grads + kOB3;
-  e = gemm<EP_WGRAD>(w3, s);
+  e = gemm<EP_WGRAD>(w3, s, w.part);
   Gemm d2 = make(b, kMlpH, kMlpOut, w.d3, kMlpOut, 1, P + kOW3, kMlpH, 1, w.d2, kMlpH);
   d2.Z = w.z2;
   if (e == hipSuccess) e = gemm<EP_GELU_GRAD>(d2, s);
   // layer 2
   Gemm w2 = make(kMlpH, kMlpH, b, w.d2, 1, kMlpH, w.a1, kMlpH, 1, grads + kOW2, kMlpH);
   w2.C2 = grads + kOB2;
-  if (e == hipSuccess) e = gemm<EP_WGRAD>(w2, s);
+  if (e == hipSuccess) e = gemm<EP_WGRAD>(w2, s, w.part);
   Gemm d1 = make(b, kMlpH, kMlpH, w.d2, kMlpH, 1, P + kOW2, kMlpH, 1, w.d1, kMlpH);
   d1.Z = w.z1;
   if (e == hipSuccess) e = gemm<EP_GELU_GRAD>(d1, s);
   // layer 1
   Gemm w1 = make(kMlpH, kMlpIn, b, w.d1, 1, kMlpH, X, kMlpIn, 1, grads + kOW1, kMlpIn);
   w1.C2 = grads + kOB1;
-  if (e == hipSuccess) e = gemm<EP_WGRAD>(w1, s);
+  if (e == hipSuccess) e = gemm<EP_WGRAD>(w1, s, w.part);
   if (e == hipSuccess) e = hipGetLastError();
   return e;
 }

@@ -47,7 +47,11 @@ struct MlpWork {
   float* d1 = nullptr;    // [cap][128] dL/dz1
   float* lrow = nullptr;  // [cap] per-row loss
   float* lsum = nullptr;  // [1]
+  // [8][128][129] chunk sums of the weight-gradient products (null: those
+  // products run unsplit)
+  float* part = nullptr;
 };
+constexpr int64_t kMlpPartFloats = 8 * 128 * 129;
 
 // Fill `grads` (device, kMlpParams) with dL/dparams for rows (X, Y) [B]
 // and write the mean loss to *loss_dev.  Deterministic.

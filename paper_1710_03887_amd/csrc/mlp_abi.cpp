@@ -22,7 +22,7 @@ int mfail(dg_mlp* m, int code, const std::string& msg) {
 }
 
 void free_work(dg::MlpWork& w) {
-  float* bufs[] = {w.x, w.y, w.z1, w.a1, w.z2, w.a2, w.yh, w.d3, w.d2, w.d1, w.lrow, w.lsum};
+  float* bufs[] = {w.x, w.y, w.z1, w.a1, w.z2, w.a2, w.yh, w.d3, w.d2, w.d1, w.lrow, w.lsum, w.part};
   for (float* b : bufs)
     if (b) (void)hipFree(b);
   w = dg::MlpWork{};
@@ -42,7 +42,8 @@ hipError_t ensure_cap(dg_mlp* m, int64_t B) {
   } want[] = {{&w.x, cap * dg::kMlpIn},   {&w.y, cap * dg::kMlpOut}, {&w.z1, cap * dg::kMlpH},
               {&w.a1, cap * dg::kMlpH},   {&w.z2, cap * dg::kMlpH},  {&w.a2, cap * dg::kMlpH},
               {&w.yh, cap * dg::kMlpOut}, {&w.d3, cap * dg::kMlpOut}, {&w.d2, cap * dg::kMlpH},
-              {&w.d1, cap * dg::kMlpH},   {&w.lrow, cap},             {&w.lsum, 1}};
+              {&w.d1, cap * dg::kMlpH},   {&w.lrow, cap},             {&w.lsum, 1},
+              {&w.part, dg::kMlpPartFloats}};
   for (auto& x : want) {
     e = hipMalloc(reinterpret_cast<void**>(x.p), size_t(x.n) * sizeof(float));
     if (e != hipSuccess) {
