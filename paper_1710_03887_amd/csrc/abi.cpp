@@ -613,18 +613,19 @@ int dg_set_curved(dg_ctx* c, const double* xyz_nodes, double tol, int64_t* n_cur
     if (n_curved_out) *n_curved_out = n;
     return DG_OK;
   }
-  // Dr, Ds, Dt packed as the MFMA A operand (lane order, zero padded); LIFT
-  // transposed, so that the lanes (one node each) read consecutive words
-  const int MT = (3 * Np + 15) / 16, KS = (Np + 3) / 4;
-  std::vector<float> D(size_t(KS) * MT * 64, 0.0f), L(size_t(Np) * NF);
+  // Dr, Ds, Dt each packed as the MFMA A operand (lane order, zero padded);
+  // LIFT transposed, so that the lanes (one node each) read consecutive words
+  const int MT = (Np + 15) / 16, KS = (Np + 3) / 4;
+  std::vector<float> D(size_t(3) * KS * MT * 64, 0.0f), L(size_t(Np) * NF);
   const std::vector<double>* Da[3] = {&c->ops.Dr, &c->ops.Ds, &c->ops.Dt};
-  for (int ks = 0; ks < KS; ++ks)
-    for (int t = 0; t < MT; ++t)
-      for (int l = 0; l < 64; ++l) {
-        const int row = 16 * t + (l & 15), j = 4 * ks + (l >> 4);
-        if (row < 3 * Np && j < Np)
-          D[(size_t(ks) * MT + t) * 64 + l] = float((*Da[row / Np])[size_t(row % Np) * Np + j]);
-      }
+  for (int a = 0; a < 3; ++a)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int t = 0; t < MT; ++t)
+        for (int l = 0; l < 64; ++l) {
+          const int row = 16 * t + (l & 15), j = 4 * ks + (l >> 4);
+          if (row < Np && j < Np)
+            D[((size_t(a) * KS + ks) * MT + t) * 64 + l] = float((*Da[a])[size_t(row) * Np + j]);
+        }
   for (int n = 0; n < Np; ++n)
     for (int i = 0; i < NF; ++i) L[size_t(i) * Np + n] = float(c->ops.LIFT[size_t(n) * NF + i]);
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -6,15 +6,17 @@
 // operator of Appendix A, Eq. 10, for constant metric terms).
 //
 // One wavefront per curved element (four per block); each wavefront stages
-// its element's state, the three Cartesian flux perturbations of every node
-// and the face jumps in its own LDS slice and synchronizes only itself.  The
-// volume contraction G[(a, n)][(d, v)] = sum_j D_a[n][j] F_dv[j] is one dense
-// product, [3 Np x Np] x [Np x 15], on MFMA f32 16x16x4 (the operator packed
-// on the host in the instruction's lane order); each node's lane then applies
-// its nine metric terms.  Curved elements are the boundary layer of a curved
-// outer surface, a small share of the mesh, so one element per wavefront
-// (rather than the stage kernel's tiles) keeps this pass simple; its time is
-// the latency of each element's chain of phases.
+// its element's state and the three Cartesian flux perturbations of every
+// node in its own LDS slice and synchronizes only itself.  The volume
+// contraction G_a[n][(d, v)] = sum_j D_a[n][j] F_dv[j] runs on MFMA f32
+// 16x16x4 one direction a at a time ([Np x Np] x [Np x 15], the operator
+// packed on the host in the instruction's lane order, the flux operand held
+// in registers); after each, the lane of node n applies its metric terms
+// d r_a / d x_d.  The face jumps stay in registers until their one-per-face
+// Lax-Friedrichs speed is known.  The slice is 5.2 KB at N = 4 (seven
+// wavefronts per SIMD).  Curved elements are a small share of the mesh, so
+// one element per wavefront (rather than the stage kernel's tiles) keeps
+// this pass simple.
 #include "curved.hpp"
 
 #include <algorithm>
@@ -58,24 +60,26 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
   constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
   constexpr int Nfp = (N + 1) * (N + 2) / 2;
   constexpr int NF = 4 * Nfp, ST = 5 * Np;
-  // MFMA tiling of the volume product: MT row tiles of (a, n), KS steps of 4 nodes
-  constexpr int MT = (3 * Np + 15) / 16, KS = (Np + 3) / 4;
-  // per-wavefront slice, 16-byte aligned regions; the product's rows (sG)
-  // reuse the space of the fluxes and face scratch, dead by then
-  constexpr int oD = (ST + 3) / 4 * 4, oF = oD + 8 * NF, oQ = oF + 16 * 4 * KS, oS = oQ + 5 * NF;
-  constexpr int scratch = (oS + NF - oF) > 16 * 16 * MT ? (oS + NF - oF) : 16 * 16 * MT;
-  constexpr int kSlice = (oF + scratch + 3) / 4 * 4;
+  static_assert(Np <= 64, "one node per lane");
+  // MFMA tiling of each direction's product: MT row tiles of n, KS steps of 4 nodes
+  constexpr int MT = (Np + 15) / 16, KS = (Np + 3) / 4;
+  constexpr int NFL = (NF + 63) / 64;   // face nodes per lane
+  // per-wavefront slice (floats): state [5][Np] | lifted jumps [5][NF] |
+  // fluxes [4 KS][16], later one direction's product [16 MT][16] | face speeds
+  constexpr int oD = (ST + 3) / 4 * 4, oF = (oD + 5 * NF + 3) / 4 * 4;
+  constexpr int fg = 16 * 4 * KS > 16 * 16 * MT ? 16 * 4 * KS : 16 * 16 * MT;
+  constexpr int oS = oF + fg;
+  constexpr int kSlice = (oS + NF + 3) / 4 * 4;
   __shared__ __align__(16) float lds[kWavesC * kSlice];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t ic = int64_t(blockIdx.x) * kWavesC + w;
   if (ic >= cv.n) return;  // whole wavefront; no block-wide barrier below
   const int64_t k = cv.elem[ic];
   float* sq = lds + w * kSlice;  // [5][Np] state q'
-  float* sdF = sq + oD;          // [NF][8]: n.(F- - F+), then the lifted jump (padded)
+  float* sdF = sq + oD;          // [5][NF] lifted jumps
   float* sF = sq + oF;           // [4 KS][16]: [3 (x,y,z)][5] flux perturbations, zero padded
-  float* sdQ = sq + oQ;          // [NF][5] q- - q+
+  float* sG = sq + oF;           // [16 MT][16]: one direction's product (after the fluxes)
   float* sS = sq + oS;           // [NF] max(|u.n| + c) of both sides
-  float* sG = sq + oF;           // [16 MT][16]: the volume product (after the MFMAs)
   const Phys& P = m.phys;
   const double tst = run ? run->t + c_rk * run->dt : t_host + c_rk * dt_host;
   const float pin = pulse_pressure(P, tst);
@@ -86,10 +90,10 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
   for (int i = lane; i < 16 * 4 * KS; i += 64)
     if (i >= 16 * Np || (i & 15) == 15) sF[i] = 0.0f;
   wave_sync();
-  for (int n = lane; n < Np; n += 64) {
+  if (lane < Np) {
     float qq[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) qq[v] = sq[v * Np + n];
+    for (int v = 0; v < 5; ++v) qq[v] = sq[v * Np + lane];
     Prim wv;
     primitive<MOVING>(P, qq, wv);
 #pragma unroll
@@ -98,15 +102,24 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
       float f[5];
       normal_flux<MOVING>(P, wv, e, f);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sF[n * 16 + d * 5 + v] = f[v];
+      for (int v = 0; v < 5; ++v) sF[lane * 16 + d * 5 + v] = f[v];
     }
   }
-  // face jumps at every face node, with that node's own normal
-  for (int i = lane; i < NF; i += 64) {
+  // face jumps at every face node, with that node's own normal (kept in
+  // registers until the face's speed is reduced)
+  float dFr[NFL][5], dQr[NFL][5], fsr[NFL];
+#pragma unroll
+  for (int it = 0; it < NFL; ++it) {
+    const int i = lane + 64 * it;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) dFr[it][v] = dQr[it][v] = 0.0f;
+    fsr[it] = 0.0f;
+    if (i >= NF) continue;
     const int f = i / Nfp, ii = i - f * Nfp;
     const int node = m.fmask[i];
-    const float* gs = cv.sg + (ic * NF + i) * 4;
-    const float nn[3] = {gs[0], gs[1], gs[2]};
+    const float4 gs = reinterpret_cast<const float4*>(cv.sg)[ic * NF + i];
+    const float nn[3] = {gs.x, gs.y, gs.z};
+    fsr[it] = gs.w;
     float qm[5], qp[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) qm[v] = sq[v * Np + node];
@@ -128,96 +141,92 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
     sS[i] = fmaxf(normal_speed<MOVING>(P, wm, nn), normal_speed<MOVING>(P, wp, nn));
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      sdF[i * 8 + v] = fm[v] - fp[v];
-      sdQ[i * 5 + v] = qm[v] - qp[v];
+      dFr[it][v] = fm[v] - fp[v];
+      dQr[it][v] = qm[v] - qp[v];
     }
   }
   wave_sync();
   // local Lax-Friedrichs jump, one lambda per face, scaled by the node's sJ/J
-  for (int i = lane; i < NF; i += 64) {
+#pragma unroll
+  for (int it = 0; it < NFL; ++it) {
+    const int i = lane + 64 * it;
+    if (i >= NF) continue;
     const int f = i / Nfp;
     float lam = 0.0f;
     for (int j = 0; j < Nfp; ++j) lam = fmaxf(lam, sS[f * Nfp + j]);
-    const float fs = cv.sg[(ic * NF + i) * 4 + 3];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) sdF[i * 8 + v] = 0.5f * fs * (sdF[i * 8 + v] - lam * sdQ[i * 5 + v]);
+    for (int v = 0; v < 5; ++v) sdF[v * NF + i] = 0.5f * fsr[it] * (dFr[it][v] - lam * dQr[it][v]);
   }
-  wave_sync();
-  // volume product on MFMA: lane l supplies A[row l%16][k l/16] (packed) and
-  // B[k l/16][col l%16] = F of node 4 ks + l/16, column l%16; it holds
-  // D[rows 4 (l/16) .. +3][col l%16] of each row tile
-  {
+  // B operand of the volume products: lane l holds F of node 4 ks + l/16,
+  // column l%16, for every step ks
+  float bv[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) bv[ks] = sF[(4 * ks + (lane >> 4)) * 16 + (lane & 15)];
+  wave_sync();  // every lane holds its operand: sG reuses the fluxes' space
+  const float* g = cv.vg + (ic * Np + (lane < Np ? lane : 0)) * 9;
+  float gm[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) gm[i] = lane < Np ? g[i] : 0.0f;
+  float r[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // G_a = D_a F: lane l supplies A[row l%16][k l/16] (packed) and holds
+    // rows 4 (l/16) .. +3, column l%16, of each row tile
     floatx4 acc[MT];
 #pragma unroll
     for (int t = 0; t < MT; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    const float* Ap = cv.D + lane;
-#pragma unroll 3
-    for (int ks = 0; ks < KS; ++ks) {
-      const float b = sF[(4 * ks + (lane >> 4)) * 16 + (lane & 15)];
+    const float* Ap = cv.D + size_t(a) * KS * MT * 64 + lane;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int t = 0; t < MT; ++t)
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ap[(ks * MT + t) * 64], b, acc[t], 0, 0, 0);
-    }
-    wave_sync();  // every lane is done with the fluxes: sG reuses their space
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ap[(ks * MT + t) * 64], bv[ks], acc[t], 0, 0, 0);
+    if (a > 0) wave_sync();  // the previous direction's rows are read
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
       for (int i = 0; i < 4; ++i) sG[(16 * t + 4 * (lane >> 4) + i) * 16 + (lane & 15)] = acc[t][i];
-  }
-  wave_sync();
-  for (int n = lane; n < Np; n += 64) {
-    float G[3][3][5];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    wave_sync();
+    if (lane < Np) {
+      // r_v -= sum_d (d r_a / d x_d) G_a[n][(d, v)]
+      float G[16];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const float4 g4 = reinterpret_cast<const float4*>(sG + (a * Np + n) * 16)[c];
-        const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (4 * c + u < 15) G[a][(4 * c + u) / 5][(4 * c + u) % 5] = gv[u];
+        const float4 g4 = reinterpret_cast<const float4*>(sG + lane * 16)[c];
+        G[4 * c] = g4.x;
+        G[4 * c + 1] = g4.y;
+        G[4 * c + 2] = g4.z;
+        G[4 * c + 3] = g4.w;
       }
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) r[v] -= gm[a * 3 + d] * G[d * 5 + v];
     }
-    const float* g = cv.vg + (ic * Np + n) * 9;
-    float gm[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) gm[i] = g[i];
-    float r[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      float div = 0.0f;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) div += gm[a * 3 + d] * G[a][d][v];
-      r[v] = -div;
-    }
+  }
+  if (lane >= Np) return;
+  const int n = lane;
 #pragma unroll 6
-    for (int i = 0; i < NF; ++i) {
-      const float l = cv.L[size_t(i) * Np + n];
-      const float4 d4 = *reinterpret_cast<const float4*>(sdF + i * 8);
-      r[0] += l * d4.x;
-      r[1] += l * d4.y;
-      r[2] += l * d4.z;
-      r[3] += l * d4.w;
-      r[4] += l * sdF[i * 8 + 4];
-    }
-    if (m.sigma) {
-      const float sgm = m.sigma[k * Np + n];
+  for (int i = 0; i < NF; ++i) {
+    const float l = cv.L[size_t(i) * Np + n];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) r[v] -= sgm * sq[v * Np + n];
-    }
+    for (int v = 0; v < 5; ++v) r[v] += l * sdF[v * NF + i];
+  }
+  if (m.sigma) {
+    const float sgm = m.sigma[k * Np + n];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const int64_t gi = k * ST + v * Np + n;
-      if (mode == MODE_RHS) {
-        out[gi] = r[v];
-      } else {
-        const float prev = a_rk != 0.0f ? cv.res_save[ic * ST + v * Np + n] : 0.0f;
-        const float rr = dt * r[v] + a_rk * prev;
-        res[gi] = rr;
-        q_out[gi] = sq[v * Np + n] + b_rk * rr;
-      }
+    for (int v = 0; v < 5; ++v) r[v] -= sgm * sq[v * Np + n];
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const int64_t gi = k * ST + v * Np + n;
+    if (mode == MODE_RHS) {
+      out[gi] = r[v];
+    } else {
+      const float prev = a_rk != 0.0f ? cv.res_save[ic * ST + v * Np + n] : 0.0f;
+      const float rr = dt * r[v] + a_rk * prev;
+      res[gi] = rr;
+      q_out[gi] = sq[v * Np + n] + b_rk * rr;
     }
   }
 }

@@ -17,9 +17,9 @@ struct CurvedSet {
   const int64_t* elem = nullptr; // [n] element ids, ascending
   const float* vg = nullptr;     // [n][Np][9] d r_a / d x_d at each node
   const float* sg = nullptr;     // [n][4][Nfp][4] unit normal, sJ/J at each face node
-  // Dr, Ds, Dt as the A operand of MFMA f32 16x16x4: [KS][MT][64], lane l of
-  // (ks, t) = D_a[n][j] for row 16 t + l%16 = a Np + n and j = 4 ks + l/16
-  // (zero outside 3 Np rows and Np columns); MT = ceil(3 Np / 16), KS = ceil(Np / 4)
+  // Dr, Ds, Dt as the A operand of MFMA f32 16x16x4: [3][KS][MT][64], lane l
+  // of (a, ks, t) = D_a[n][j] for row n = 16 t + l%16 and j = 4 ks + l/16
+  // (zero outside Np rows and columns); MT = ceil(Np / 16), KS = ceil(Np / 4)
   const float* D = nullptr;
   const float* L = nullptr;      // [4 Nfp (i)][Np (n)] = LIFT[n][i] (transposed)
   float* res_save = nullptr;     // [n][5][Np] their residual before the stage kernel
