@@ -419,6 +419,48 @@ def time_curved(dg, torch, steps=100, target_K=80_000, N=4):
     return out
 
 
+def time_learned(dg, torch, target_K=50_000, steps=200):
+    """Cost of the learned boundary closure per step: the trumpet in the box
+    with the characteristic ghost on its outer faces, and the same mesh with
+    those faces tagged learned (network with its initial weights, every face
+    inside the window, blend 0.5), both with one fixed dt.  The accuracy side
+    (the equivalent speedup) needs the sampling and training workflow and is
+    not measured here."""
+    from workloads import trumpet_domain, BC_LEARNED, BC_OUTFLOW_CHAR
+    from workloads.mlp_init import init_params
+    m = trumpet_domain("box", target_K)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    net = dg.dg_mlp_create(init_params(0), stream=stream)
+    for label in ("characteristic", "learned"):
+        bc = m["bc"].copy()
+        if label == "learned":
+            bc[bc == BC_OUTFLOW_CHAR] = BC_LEARNED
+        ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], bc, 4, gamma=1.4, rho0=1.0, p0=1.0 / 1.4,
+                               inflow_amp=0.01 / 1.4, inflow_alpha=2 * np.pi * 565.0 / 343.0)
+        if label == "learned":
+            dg.dg_set_learned_bc(ctx, net, 0.0, 0.0, 1e30, blend=0.5)
+            out["learned_faces"] = int(len(dg.dg_learned_faces(ctx)))
+        K, Np = ctx.K, ctx.Np
+        q = torch.zeros((K, 5, Np), dtype=torch.float32, device=dev)
+        res = torch.zeros_like(q)
+        dt = 8e-5
+        t = dg.dg_run_fixed(ctx, q, res, 20, dt, 0.0, stream=stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        dg.dg_run_fixed(ctx, q, res, steps, dt, t, stream=stream)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / steps
+        out[label] = {"K": K, "ms_per_step": ms, "value": 5 * K * Np * 5 / (ms * 1e-3)}
+        dg.dg_destroy(ctx)
+    dg.dg_mlp_destroy(net)
+    out["steps"] = steps
+    out["cost_ratio"] = out["learned"]["ms_per_step"] / out["characteristic"]["ms_per_step"]
+    return out
+
+
 def time_mlp(dg, torch, rows=65_536, batch=4096, steps=40):
     """The closure's network (78-128-128-75, GELU): Adam steps on 4,096-row
     minibatches of a 65,536-row synthetic set (the training configuration),
@@ -464,9 +506,9 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--form", choices=("fp32", "bf16"), default="fp32",
                     help="form of the headline measurement")
-    ap.add_argument("--also", default="bf16,batch,n5,probes,quadrature,curved,mlp",
+    ap.add_argument("--also", default="bf16,batch,n5,probes,quadrature,curved,mlp,learned",
                     help="comma list of extra measurements: bf16, fp32, batch, n5, probes, "
-                         "quadrature, curved, mlp (or empty)")
+                         "quadrature, curved, mlp, learned (or empty)")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--n5-steps", type=int, default=100,
                     help="steps per form of the 1.17M-tet N = 5 precision workload")
@@ -518,6 +560,8 @@ def main():
             extra["curved"] = time_curved(dg, torch)
         elif name == "mlp":
             extra["mlp"] = time_mlp(dg, torch)
+        elif name == "learned":
+            extra["learned"] = time_learned(dg, torch)
     if args.copy_mb:
         n = args.copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
