@@ -3,9 +3,10 @@
 // Fused stage kernel.  A block of four wavefronts owns a tile of 16
 // consecutive elements at a time (persistent grid; each of the 8 XCDs sweeps
 // a contiguous range of tiles so that neighbour traces mostly hit its L2):
-//   A. the tile's state q' [16][5][Np] and every exterior face trace it needs
-//      are requested at once with asynchronous global->LDS copies (the
-//      neighbour gathers never stall a wavefront one face at a time);
+//   A. the tile's state q' [16][5][Np] (asynchronous global->LDS copies) and
+//      every exterior face trace it needs (into the registers of the lane
+//      that uses it; LDS copies in the split-BF16 form) are requested at once,
+//      so the neighbour gathers never stall a wavefront one face at a time;
 //   B. the local Lax-Friedrichs speed of each element face,
 //      max over its nodes and both sides of |u.n| + c, is reduced in LDS;
 //   C. the contraction is split over the four wavefronts along its length:
@@ -201,6 +202,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 
   float rate_best = 0.0f;   // time-step reduction over this block's tiles
   unsigned rate_bad = 0u;
+  // FP32: the exterior traces go straight into the registers of the lane
+  // that uses them in the surface pass (the split-BF16 form re-reads them
+  // from LDS in the contraction pass, so it stages them there)
+  constexpr bool TR_REG = PREC == PREC_FP32;
+  float trv[TR_REG ? kFQ : 1][5];
   for (int64_t tile = c0 + jb; tile < c1; tile += Gx) {
     // at N >= 5, thread indices the compiler must treat as new each tile:
     // otherwise it hoists every lane-dependent address out of the tile loop
@@ -221,7 +227,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
     for (int kq = 0; kq < kFQ; ++kq) {
       const int fq = w + kWaves * kq;
-      if (goff[kq] != -1) {
+      if (TR_REG) {
+        // (no load on boundary faces: goff = -1 points the address at q_in)
+        const float* src = goff[kq] >= 0 ? q_in + goff[kq]
+                           : (goff[kq] < -1 ? m.lghost + (-2 - goff[kq]) : q_in);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) trv[TR_REG ? kq : 0][v] = goff[kq] != -1 ? src[v * Np] : 0.0f;
+      } else if (goff[kq] != -1) {
         const float* src = goff[kq] >= 0 ? q_in + goff[kq] : m.lghost + (-2 - goff[kq]);
 #pragma unroll
         for (int v = 0; v < 5; ++v)
@@ -297,7 +309,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       float* slot = sP + fq * 5 * 64 + lane;
       if (nb >= 0 || (m.lghost && ((-nb) & 7) == BC_LEARNED)) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qp[v] = slot[v * 64];
+        for (int v = 0; v < 5; ++v) qp[v] = TR_REG ? trv[TR_REG ? kq : 0][v] : slot[v * 64];
       } else {
         ghost(P, -nb, qm, wm, n, pin, qp);
       }
