@@ -31,12 +31,19 @@ SEGMENTS = 5    # timed steps are split into this many event-timed dg_run calls
 RK4A2, RK4B2 = -567301805773.0 / 1357537059087.0, 5161836677717.0 / 13612068292357.0
 
 
-def stage_bytes(K, Np, reads_res=True):
+def geometry_bytes(variant):
+    """Geometry bytes per element a stage kernel reads: 9 metric terms and
+    4 x (normal, Fscale), FP32 for the tile-cooperative kernel (variant 0),
+    FP64 for the role-specialized one."""
+    return (9 + 16) * (4 if variant == 0 else 8)
+
+
+def stage_bytes(K, Np, reads_res=True, variant=0):
     """Algorithmic HBM bytes of one fused stage: state in, residual in/out,
-    state out (FP32), FP64 geometry (9 metric + 4 x (normal, Fscale)) and
-    connectivity (4 int32 neighbours + 4 bytes of face/orientation)."""
+    state out (FP32), geometry (geometry_bytes) and connectivity (4 int32
+    neighbours + 4 bytes of face/orientation)."""
     passes = 4 if reads_res else 3
-    return K * (passes * 5 * Np * 4 + (9 + 16) * 8 + 4 * 4 + 4)
+    return K * (passes * 5 * Np * 4 + geometry_bytes(variant) + 4 * 4 + 4)
 
 
 def kernel_source_hash():
@@ -173,7 +180,8 @@ def time_single(dg, torch, m, N, form, steps, warmup, kernel_iters):
         torch.cuda.synchronize()
         batches.append(k0.elapsed_time(k1) * 1e-3 / kernel_iters)
     kernel_s = float(np.median(batches))
-    # dg_rhs alone (q in, rhs out: 40 Np + 220 algorithmic bytes per element)
+    # dg_rhs alone (q in, rhs out, geometry and connectivity: 40 Np + 120
+    # algorithmic bytes per element with the tile-cooperative kernel)
     r = torch.empty_like(q)
     r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     r0.record(stream)
@@ -182,9 +190,9 @@ def time_single(dg, torch, m, N, form, steps, warmup, kernel_iters):
     r1.record(stream)
     torch.cuda.synchronize()
     rhs_s = r0.elapsed_time(r1) * 1e-3 / kernel_iters
-    rhs_bytes = K * (40 * Np + 220)
-    nbytes = stage_bytes(K, Np, True)
     variant = dg.dg_get_kernel(ctx)
+    rhs_bytes = K * (40 * Np + geometry_bytes(variant) + 20)
+    nbytes = stage_bytes(K, Np, True, variant)
     return {"K": K, "N": N, "Np": Np, "dof": dof, "ms": ms, "wall_s": wall, "t_end": t_end,
             "dt_last": dt_last, "value": dof * 5 * steps / (ms * 1e-3), "kernel_s": kernel_s,
             "segments": {"steps": seg, "ms": seg_ms, "median_value": float(np.median(seg_rate)),
@@ -193,7 +201,7 @@ def time_single(dg, torch, m, N, form, steps, warmup, kernel_iters):
             "kernel_batches_ms": [b * 1e3 for b in batches],
             "bytes": nbytes, "achieved": nbytes / kernel_s / 1e9, "blocks_per_cu": bpc,
             "kernel_variant": variant,
-            "rhs_ms": rhs_s * 1e3, "rhs_GBs": rhs_bytes / rhs_s / 1e9,
+            "rhs_ms": rhs_s * 1e3, "rhs_GBs": rhs_bytes / rhs_s / 1e9, "rhs_bytes": rhs_bytes,
             "kernel": ("stage_kernel" if variant == 0 else "spec_stage_kernel") +
                       f"<{N},MODE_STAGE>"}
 
@@ -598,7 +606,7 @@ def main():
                      "bytes_per_launch": r["bytes"],
                      "dg_rhs": {"ms": r["rhs_ms"], "achieved": r["rhs_GBs"],
                                 "frac": r["rhs_GBs"] / HBM_PEAK_GBS,
-                                "bytes_per_launch": r["K"] * (40 * r["Np"] + 220)}},
+                                "bytes_per_launch": r["rhs_bytes"]}},
         "forms": extra,
     }
     if not args.no_cpu_baseline:

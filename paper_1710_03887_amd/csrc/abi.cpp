@@ -93,6 +93,15 @@ int build_device(dg_ctx* c, hipStream_t s) {
       for (int d = 0; d < 3; ++d) sgeo[size_t(k) * 16 + f * 4 + d] = mh.nrm[size_t(k) * 12 + f * 3 + d];
       sgeo[size_t(k) * 16 + f * 4 + 3] = mh.Fscale[size_t(k) * 4 + f];
     }
+  // FP32 geometry of the tile-cooperative stage kernel: per tile of 16
+  // elements, component-major [25][16], zero past the last element
+  const int64_t ntiles = (K + 15) / 16;
+  std::vector<float> geo32(size_t(ntiles) * 16 * 25, 0.0f);
+  for (int64_t k = 0; k < K; ++k) {
+    float* g = &geo32[size_t(k / 16) * 400 + size_t(k % 16)];
+    for (int i = 0; i < 9; ++i) g[i * 16] = float(mh.drst_dx[size_t(k) * 9 + i]);
+    for (int j = 0; j < 16; ++j) g[(9 + j) * 16] = float(sgeo[size_t(k) * 16 + j]);
+  }
   std::vector<int32_t> nbr(size_t(K) * 4);
   std::vector<uint8_t> finfo(size_t(K) * 4);
   c->lface_host.clear();
@@ -136,6 +145,9 @@ int build_device(dg_ctx* c, hipStream_t s) {
   if ((rc = upload(c, ops.nbr_node.data(), ops.nbr_node.size(), &dNN, s))) return rc;
   if ((rc = upload(c, mh.drst_dx.data(), mh.drst_dx.size(), &dV, s))) return rc;
   if ((rc = upload(c, sgeo.data(), sgeo.size(), &dS, s))) return rc;
+  float* dG32;
+  if ((rc = upload(c, geo32.data(), geo32.size(), &dG32, s))) return rc;
+  c->dm.geo32 = dG32;
   if ((rc = upload(c, nbr.data(), nbr.size(), &dN, s))) return rc;
   if ((rc = upload(c, finfo.data(), finfo.size(), &dFi, s))) return rc;
   if ((rc = upload<float>(c, nullptr, size_t(K) * 5 * Np, &c->qbuf, s))) return rc;

@@ -71,9 +71,11 @@ struct Shape {
   static constexpr int oQ = oTab + tabFloats;        // [16][5][Np] state tile
   static constexpr int oR = oQ + kTileE * ST;        // [16][5][Np] residual tile
   static constexpr int oP = oR + kTileE * ST;        // exterior traces / reduction
-  static constexpr int oG = oP + scratch;            // FP64 [16][9] metric, [16][16] faces
-  static constexpr int oF = oG + kTileE * 25 * 2;    // FP32 [16][17] faces, [16][9] metric
-  static constexpr int oL = oF + kTileE * 26;        // [16][4] face speeds
+  // FP32 geometry of the tile, component-major [25][16]: the metric terms
+  // d(r,s,t)/d(x,y,z) (components 0..8), then nx, ny, nz, Fscale of each face
+  static constexpr int oG = oP + scratch;
+  static constexpr int oL = oG + kTileE * 25;        // [16][4] face speeds
+  static_assert(oG % 4 == 0, "16-byte chunks of the geometry copy");
   // split-BF16: n.(F- - F+) gets its own region and q- - q+ is recomputed
   // (frees registers for the BF16 operands)
   static constexpr bool DQ_LDS = PREC == PREC_BF16;
@@ -132,10 +134,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   float* sQ = lds + S::oQ;
   float* sR = lds + S::oR;
   float* sP = lds + S::oP;
-  const double* sVg = reinterpret_cast<const double*>(lds + S::oG);   // [16][9]
-  const double* sSg = sVg + kTileE * 9;                               // [16][16]
-  float* sFg = lds + S::oF;             // [16][17]: n, Fscale per face (row padded)
-  float* sMg = sFg + kTileE * 17;       // [16][9]: metric
+  const float* sGe = lds + S::oG;       // [25][16] geometry: component c of element e at c*16 + e
   unsigned* sL = reinterpret_cast<unsigned*>(lds + S::oL);
   const Phys& P = m.phys;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -255,35 +254,26 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                                              (lds_ptr_t)(sR + j * 256), 16, 0, 0);
         }
       }
-      // FP64 geometry of the tile: 1152 + 2048 contiguous bytes, 16-byte chunks
+      // FP32 geometry of the tile, already in its LDS layout: 1600
+      // contiguous bytes, 16-byte chunks
       if (w == kWaves - 1) {
-        const char* vsrc = reinterpret_cast<const char*>(m.vgeo + k0 * 9);
-        const char* ssrc = reinterpret_cast<const char*>(m.sgeo + k0 * 16);
+        const char* gsrc = reinterpret_cast<const char*>(m.geo32 + tile * kTileE * 25);
         char* gdst = reinterpret_cast<char*>(lds + S::oG);
-        __builtin_amdgcn_global_load_lds((void*)(vsrc + 16 * lane), (lds_ptr_t)(gdst), 16, 0, 0);
-        if (lane < 8)
-          __builtin_amdgcn_global_load_lds((void*)(vsrc + 1024 + 16 * lane), (lds_ptr_t)(gdst + 1024),
+        __builtin_amdgcn_global_load_lds((void*)(gsrc + 16 * lane), (lds_ptr_t)(gdst), 16, 0, 0);
+        if (lane < 36)
+          __builtin_amdgcn_global_load_lds((void*)(gsrc + 1024 + 16 * lane), (lds_ptr_t)(gdst + 1024),
                                            16, 0, 0);
-        __builtin_amdgcn_global_load_lds((void*)(ssrc + 16 * lane), (lds_ptr_t)(gdst + 1152), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((void*)(ssrc + 1024 + 16 * lane), (lds_ptr_t)(gdst + 2176),
-                                         16, 0, 0);
       }
     } else {
       for (int i = tid_t; i < kTileE * ST; i += kThreads) {
         sQ[i] = (i < ne * ST) ? qg[i] : 0.0f;
         if (want_res) sR[i] = (i < ne * ST) ? res[k0 * ST + i] : 0.0f;
       }
-      double* gd = reinterpret_cast<double*>(lds + S::oG);
-      for (int i = tid_t; i < kTileE * 9; i += kThreads) gd[i] = (i < ne * 9) ? m.vgeo[k0 * 9 + i] : 0.0;
-      for (int i = tid_t; i < kTileE * 16; i += kThreads)
-        gd[kTileE * 9 + i] = (i < ne * 16) ? m.sgeo[k0 * 16 + i] : 0.0;
+      // (the geometry array is zero past the last element)
+      for (int i = tid_t; i < kTileE * 25; i += kThreads) lds[S::oG + i] = m.geo32[tile * kTileE * 25 + i];
     }
     load_conn(tile + Gx, nbN, fiN);  // next tile's connectivity, in flight meanwhile
     __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    // geometry to FP32 with padded rows (avoids 16-way bank conflicts)
-    if (tid_t < kTileE * 16) sFg[(tid_t >> 4) * 17 + (tid_t & 15)] = float(sSg[tid_t]);
-    if (tid_t < kTileE * 9) sMg[tid_t] = float(sVg[tid_t]);
     gather_offsets(tile + Gx);
     __syncthreads();
 
@@ -297,8 +287,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       const int fq = w + kWaves * kq;
       if (fq >= S::NFQ) break;
       const int i = 4 * fq + g, f = i / Nfp;
-      const float* gf = sFg + e * 17 + f * 4;
-      const float n[3] = {gf[0], gf[1], gf[2]};
+      const float n[3] = {sGe[(9 + f * 4) * kTileE + e], sGe[(10 + f * 4) * kTileE + e],
+                          sGe[(11 + f * 4) * kTileE + e]};
       const int node = sFm[i];
       float qm[5], qp[5];
 #pragma unroll
@@ -345,7 +335,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 
     float gm[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) gm[i] = sMg[e * 9 + i];
+    for (int i = 0; i < 9; ++i) gm[i] = sGe[i * kTileE + e];
     if (PREC == PREC_BF16) {
       // volume on BF16 MFMA: D (hi, lo) x F' (hi, lo), lo*lo dropped
       const bf16x8* Ab = reinterpret_cast<const bf16x8*>(m.Abf);
@@ -439,7 +429,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       if (fq >= S::NFQ) break;
       const int i = 4 * fq + g, f = i / Nfp;
       const float lam = __uint_as_float(sL[e * 4 + f]);
-      const float hs = valid ? 0.5f * sFg[e * 17 + f * 4 + 3] : 0.0f;
+      const float hs = valid ? 0.5f * sGe[(12 + f * 4) * kTileE + e] : 0.0f;
       const float* slot = sP + fq * 5 * 64 + lane;
       float dF[5];
       if (S::DQ_LDS) {
@@ -538,7 +528,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
           const float u = P.u0[d] + wv.du[d];
           sp2 += u * u;
         }
-        const float rate = P.half_N1sq * sFg[eo * 17 + f * 4 + 3] *
+        const float rate = P.half_N1sq * sGe[(12 + f * 4) * kTileE + eo] *
                            (sqrtf(sp2) + sqrtf(P.gamma * wv.p / wv.rho));
         if (!(wv.rho > 0.0f) || !(wv.p > 0.0f) || !(rate == rate)) rate_bad = 1u;
         else rate_best = fmaxf(rate_best, rate);

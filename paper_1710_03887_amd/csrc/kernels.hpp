@@ -23,6 +23,10 @@ struct DeviceMesh {
   const uint8_t* nbr_node = nullptr;  // [4][4][6][Nfp]
   const double* vgeo = nullptr;     // [K][9]   d(r,s,t)/d(x,y,z)
   const double* sgeo = nullptr;     // [K][4][4] nx ny nz Fscale
+  // the same geometry in FP32 for the tile-cooperative stage kernel, per
+  // tile of 16 elements component-major: [tiles][25][16] (the 9 metric
+  // terms, then nx, ny, nz, Fscale of faces 0..3), zero past element K - 1
+  const float* geo32 = nullptr;
   const int32_t* nbr = nullptr;     // [K][4] neighbour element, or -tag
   const uint8_t* finfo = nullptr;   // [K][4] neighbour face | orientation << 2
   // learned ghost traces [n_learned][5][Np] (nodes 0..Nfp-1), or null; a
