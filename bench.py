@@ -530,7 +530,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the element-partitioned multi-GPU path "
-              "(per-stage face-trace exchange) is a design, not part of this build.",
+              "(per-stage face-trace exchange) is designed but not implemented.",
               file=sys.stderr)
         sys.exit(2)
 

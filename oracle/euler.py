@@ -169,7 +169,7 @@ def face_traces(mesh, q, t, phys, learned=None):
 
 def rhs(mesh, q, t, phys, learned=None, pointwise_lambda=False, sigma=None):
     """f(q) of Eq. 12 for the whole mesh: returns dq/dt [K, 5, Np].  With
-    sigma [K, Np] (an absorbing layer, this build's addition), every node
+    sigma [K, Np] (an absorbing layer, an addition to the method), every node
     also relaxes towards the ambient state: - sigma (q - q0)."""
     ref = mesh.ref
     g = phys.gamma

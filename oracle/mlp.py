@@ -20,7 +20,7 @@ Parameters are one flat vector in the order W1 (row-major, out x in), b1,
 W2, b2, W3, b3.  Trace layout inside x and y: variable-major,
 x[v * Nfp + i] for variable v at face node i, then the normal (x only).
 
-The closure itself is this build's addition to the method (the paper's
+The closure itself is an addition to the method (the paper's
 boundary treatments are the pass-through and characteristic ghosts of
 Section 2); nothing here reproduces a formula of the paper.
 """
