@@ -441,15 +441,14 @@ int dg_set_damping(dg_ctx* ctx, const float* sigma);
  * when the metric terms are constant; dF the local Lax-Friedrichs jump with
  * each face node's own normal, one lambda per face).  The time-step rule
  * keeps each element's straight-sided Fscale.  Curved elements are computed
- * by a separate pass after the stage kernel (which also writes them), so the
- * straight elements keep the full-speed path.  Copies what it needs; the
- * host array may be freed on return.  NULL clears the curved set.  Applies
- * to dg_rhs, dg_step, dg_stage, the runs and dg_autotune of this context;
- * dg_probe_setup, called after it, finds a point's reference coordinates in
- * a curved element by inverting that element's map (Newton's method from
- * the straight-sided estimate; the element itself is the one the
- * straight-sided geometry gives).  On a host-only context the curved set is
- * checked and kept for probe location only.
+ * by a separate pass after the stage kernel, which leaves their outputs and
+ * their share of the time-step rate to it, so the straight elements keep
+ * the full-speed path.  Copies what it needs; the host array may be freed on
+ * return.  NULL clears the curved set.  Applies to dg_rhs, dg_step,
+ * dg_stage, the runs and dg_autotune of this context; dg_probe_setup,
+ * called after it, locates points in curved elements by inverting their
+ * maps (see there).  On a host-only context the curved set is checked and
+ * kept for probe location only.
  * n_curved_out (may be NULL) receives the number of curved elements.
  * Errors: DG_EINVAL for tol <= 0, a context with the quadrature scheme or a
  * learned closure, a node Jacobian <= 0, or node positions that do not

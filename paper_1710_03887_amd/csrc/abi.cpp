@@ -58,6 +58,7 @@ void free_curved(dg_ctx* c) {
   for (void* p : c->curved_allocs) (void)hipFree(p);
   c->curved_allocs.clear();
   c->curved = dg::CurvedSet{};
+  c->dm.curved_flag = nullptr;
   c->curved_elem_host.clear();
   c->curved_x_host.clear();
 }
@@ -203,16 +204,13 @@ hipError_t stage(dg_ctx* c, int mode, const float* q_in, float* q_out, float* re
   }
   if (c->curved.n == 0)
     return dg::launch_stage(c->dm, mode, q_in, q_out, res, out, a, b, cc, t, dt, run, rate_out, s);
-  // curved elements: their residual is kept before the stage kernel
-  // overwrites it, then their own pass replaces what the stage kernel wrote
-  // for them, and the time-step rate is reduced from the finished state
-  hipError_t e = hipSuccess;
-  if (mode == dg::MODE_STAGE && a != 0.0f) e = dg::launch_curved_save(c->curved, c->dm, res, s);
+  // curved elements: the stage kernel leaves their outputs and their share
+  // of the time-step rate to their own pass
+  hipError_t e = dg::launch_stage(c->dm, mode, q_in, q_out, res, out, a, b, cc, t, dt, run,
+                                  rate_out, s);
   if (e == hipSuccess)
-    e = dg::launch_stage(c->dm, mode, q_in, q_out, res, out, a, b, cc, t, dt, run, 0, s);
-  if (e == hipSuccess)
-    e = dg::launch_curved(c->curved, c->dm, mode, q_in, q_out, res, out, a, b, cc, t, dt, run, s);
-  if (e == hipSuccess && run && rate_out) e = dg::launch_rate(c->dm, q_out, run, s);
+    e = dg::launch_curved(c->curved, c->dm, mode, q_in, q_out, res, out, a, b, cc, t, dt, run,
+                          rate_out, s);
   return e;
 }
 
@@ -640,12 +638,15 @@ int dg_set_curved(dg_ctx* c, const double* xyz_nodes, double tol, int64_t* n_cur
         }
   for (int n = 0; n < Np; ++n)
     for (int i = 0; i < NF; ++i) L[size_t(i) * Np + n] = float(c->ops.LIFT[size_t(n) * NF + i]);
+  // per element: 1 for the curved ones (the stage kernels leave them alone)
+  std::vector<uint8_t> flag(size_t(c->dm.K), 0);
+  for (const int64_t k : elems) flag[size_t(k)] = 1;
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* p[6] = {};
   const size_t bytes[6] = {size_t(n) * sizeof(int64_t), vg.size() * sizeof(float),
                            sg.size() * sizeof(float), D.size() * sizeof(float),
-                           L.size() * sizeof(float), size_t(n) * 5 * Np * sizeof(float)};
-  const void* src[6] = {elems.data(), vg.data(), sg.data(), D.data(), L.data(), nullptr};
+                           L.size() * sizeof(float), flag.size()};
+  const void* src[6] = {elems.data(), vg.data(), sg.data(), D.data(), L.data(), flag.data()};
   for (int i = 0; i < 6; ++i) {
     const hipError_t e = hipMalloc(&p[i], bytes[i]);
     if (e != hipSuccess) {
@@ -656,7 +657,7 @@ int dg_set_curved(dg_ctx* c, const double* xyz_nodes, double tol, int64_t* n_cur
   }
   for (int i = 0; i < 6; ++i) c->curved_allocs.push_back(p[i]);
   hipError_t e = hipSuccess;
-  for (int i = 0; i < 5 && e == hipSuccess; ++i)
+  for (int i = 0; i < 6 && e == hipSuccess; ++i)
     e = hipMemcpyAsync(p[i], src[i], bytes[i], hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors end here
   if (e != hipSuccess) {
@@ -669,7 +670,7 @@ int dg_set_curved(dg_ctx* c, const double* xyz_nodes, double tol, int64_t* n_cur
   c->curved.sg = static_cast<const float*>(p[2]);
   c->curved.D = static_cast<const float*>(p[3]);
   c->curved.L = static_cast<const float*>(p[4]);
-  c->curved.res_save = static_cast<float*>(p[5]);
+  c->dm.curved_flag = static_cast<const uint8_t*>(p[5]);
   if (n_curved_out) *n_curved_out = n;
   return DG_OK;
 }

@@ -42,21 +42,11 @@ __device__ __forceinline__ float pulse_pressure(const Phys& P, double t) {
   return 0.0f;
 }
 
-__global__ __launch_bounds__(256) void curved_save_kernel(CurvedSet cv, int ST,
-                                                          const float* __restrict__ res) {
-  const int64_t total = cv.n * ST;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t c = i / ST;
-    cv.res_save[i] = res[cv.elem[c] * ST + (i - c * ST)];
-  }
-}
-
 template <int N, bool MOVING>
 __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
     DeviceMesh m, CurvedSet cv, int mode, const float* __restrict__ q_in, float* __restrict__ q_out,
     float* __restrict__ res, float* __restrict__ out, float a_rk, float b_rk, double c_rk,
-    double t_host, double dt_host, const RunScalars* run) {
+    double t_host, double dt_host, RunScalars* run, int rate_out) {
   constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
   constexpr int Nfp = (N + 1) * (N + 2) / 2;
   constexpr int NF = 4 * Nfp, ST = 5 * Np;
@@ -204,69 +194,104 @@ __global__ __launch_bounds__(64 * kWavesC) void curved_kernel(
         for (int d = 0; d < 3; ++d) r[v] -= gm[a * 3 + d] * G[d * 5 + v];
     }
   }
-  if (lane >= Np) return;
   const int n = lane;
+  if (n < Np) {
 #pragma unroll 6
-  for (int i = 0; i < NF; ++i) {
-    const float l = cv.L[size_t(i) * Np + n];
+    for (int i = 0; i < NF; ++i) {
+      const float l = cv.L[size_t(i) * Np + n];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) r[v] += l * sdF[v * NF + i];
-  }
-  if (m.sigma) {
-    const float sgm = m.sigma[k * Np + n];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) r[v] -= sgm * sq[v * Np + n];
-  }
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const int64_t gi = k * ST + v * Np + n;
-    if (mode == MODE_RHS) {
-      out[gi] = r[v];
-    } else {
-      const float prev = a_rk != 0.0f ? cv.res_save[ic * ST + v * Np + n] : 0.0f;
-      const float rr = dt * r[v] + a_rk * prev;
-      res[gi] = rr;
-      q_out[gi] = sq[v * Np + n] + b_rk * rr;
+      for (int v = 0; v < 5; ++v) r[v] += l * sdF[v * NF + i];
     }
+    if (m.sigma) {
+      const float sgm = m.sigma[k * Np + n];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) r[v] -= sgm * sq[v * Np + n];
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const int64_t gi = k * ST + v * Np + n;
+      if (mode == MODE_RHS) {
+        out[gi] = r[v];
+      } else {
+        // the stage kernel leaves the element's residual in place
+        const float prev = a_rk != 0.0f ? res[gi] : 0.0f;
+        const float rr = dt * r[v] + a_rk * prev;
+        const float qn = sq[v * Np + n] + b_rk * rr;
+        res[gi] = rr;
+        q_out[gi] = qn;
+        sq[v * Np + n] = qn;   // (this lane's own node)
+      }
+    }
+  }
+  if (mode != MODE_STAGE || !run || !rate_out) return;
+  // the element's share of the next time-step rate, from its new state: max
+  // over face nodes of (N+1)^2/2 Fscale (|u| + c), Fscale of the
+  // straight-sided element (as for every other element)
+  wave_sync();
+  float best = 0.0f;
+  unsigned bad = 0u;
+#pragma unroll
+  for (int it = 0; it < NFL; ++it) {
+    const int i = lane + 64 * it;
+    if (i >= NF) continue;
+    const int f = i / Nfp, node = m.fmask[i];
+    float qq[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) qq[v] = sq[v * Np + node];
+    Prim wv;
+    primitive<MOVING>(P, qq, wv);
+    float sp2 = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float u = P.u0[d] + wv.du[d];
+      sp2 += u * u;
+    }
+    const float rate = P.half_N1sq * float(m.sgeo[k * 16 + f * 4 + 3]) *
+                       (sqrtf(sp2) + sqrtf(P.gamma * wv.p / wv.rho));
+    if (!(wv.rho > 0.0f) || !(wv.p > 0.0f) || !(rate == rate)) bad = 1u;
+    else best = fmaxf(best, rate);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    best = fmaxf(best, __shfl_xor(best, off));
+    bad |= __shfl_xor(bad, off);
+  }
+  if (lane == 0) {
+    // thousands of small blocks: spread over the run's rate slots
+    atomicMax(&run->rate_part[ic & (kRateParts - 1)], __float_as_uint(best));
+    if (bad) atomicOr(&run->bad, 1u);
   }
 }
 
 template <int N>
 hipError_t curved_dispatch(const CurvedSet& cv, const DeviceMesh& m, int mode, const float* q_in,
                            float* q_out, float* res, float* out, float a, float b, double c,
-                           double t_host, double dt_host, const RunScalars* run, hipStream_t s) {
+                           double t_host, double dt_host, RunScalars* run, int rate_out,
+                           hipStream_t s) {
   const int blocks = int((cv.n + kWavesC - 1) / kWavesC);
   const bool moving = m.phys.u0[0] != 0.0f || m.phys.u0[1] != 0.0f || m.phys.u0[2] != 0.0f;
   if (moving)
     curved_kernel<N, true><<<blocks, 64 * kWavesC, 0, s>>>(m, cv, mode, q_in, q_out, res, out, a, b,
-                                                           c, t_host, dt_host, run);
+                                                           c, t_host, dt_host, run, rate_out);
   else
     curved_kernel<N, false><<<blocks, 64 * kWavesC, 0, s>>>(m, cv, mode, q_in, q_out, res, out, a, b,
-                                                            c, t_host, dt_host, run);
+                                                            c, t_host, dt_host, run, rate_out);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_curved_save(const CurvedSet& cv, const DeviceMesh& m, const float* res,
-                              hipStream_t s) {
-  if (cv.n <= 0) return hipSuccess;
-  const int64_t total = cv.n * 5 * m.Np;
-  const int blocks = int(std::min<int64_t>((total + 255) / 256, 4096));
-  curved_save_kernel<<<blocks, 256, 0, s>>>(cv, 5 * m.Np, res);
-  return hipGetLastError();
-}
-
 hipError_t launch_curved(const CurvedSet& cv, const DeviceMesh& m, int mode, const float* q_in,
                          float* q_out, float* res, float* out, float a, float b, double c,
-                         double t_host, double dt_host, const RunScalars* run, hipStream_t s) {
+                         double t_host, double dt_host, RunScalars* run, int rate_out,
+                         hipStream_t s) {
   if (cv.n <= 0) return hipSuccess;
   switch (m.N) {
-    case 1: return curved_dispatch<1>(cv, m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, s);
-    case 2: return curved_dispatch<2>(cv, m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, s);
-    case 3: return curved_dispatch<3>(cv, m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, s);
-    case 4: return curved_dispatch<4>(cv, m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, s);
-    case 5: return curved_dispatch<5>(cv, m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, s);
+    case 1: return curved_dispatch<1>(cv, m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out, s);
+    case 2: return curved_dispatch<2>(cv, m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out, s);
+    case 3: return curved_dispatch<3>(cv, m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out, s);
+    case 4: return curved_dispatch<4>(cv, m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out, s);
+    case 5: return curved_dispatch<5>(cv, m, mode, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out, s);
     default: return hipErrorInvalidValue;
   }
 }

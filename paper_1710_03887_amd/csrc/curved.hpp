@@ -22,18 +22,16 @@ struct CurvedSet {
   // (zero outside Np rows and columns); MT = ceil(Np / 16), KS = ceil(Np / 4)
   const float* D = nullptr;
   const float* L = nullptr;      // [4 Nfp (i)][Np (n)] = LIFT[n][i] (transposed)
-  float* res_save = nullptr;     // [n][5][Np] their residual before the stage kernel
 };
-
-// res_save[c] = res[elem[c]] (before a stage kernel overwrites them).
-hipError_t launch_curved_save(const CurvedSet& cv, const DeviceMesh& m, const float* res,
-                              hipStream_t s);
 
 // The curved elements' share of one right-hand side or LSERK stage, with the
 // contract of launch_stage (MODE_RHS: out = f(q_in); MODE_STAGE:
-// res = a res_save + dt f(q_in), q_out = q_in + b res); no rate reduction.
+// res = a res + dt f(q_in), q_out = q_in + b res), after a stage kernel that
+// left these elements' outputs alone (DeviceMesh::curved_flag); with run and
+// rate_out set, also their share of the next step's time-step rate.
 hipError_t launch_curved(const CurvedSet& cv, const DeviceMesh& m, int mode, const float* q_in,
                          float* q_out, float* res, float* out, float a, float b, double c,
-                         double t_host, double dt_host, const RunScalars* run, hipStream_t s);
+                         double t_host, double dt_host, RunScalars* run, int rate_out,
+                         hipStream_t s);
 
 }  // namespace dg

@@ -157,12 +157,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const int64_t c0 = ntiles * x / nX, c1 = ntiles * (x + 1) / nX;
 
   // connectivity of a lane's element, one tile ahead: 4 neighbours + packed
-  // (neighbour face | orientation << 2) bytes
-  auto load_conn = [&](int64_t t, int4& nb4, unsigned& fi4) {
+  // (neighbour face | orientation << 2) bytes, and whether it is curved
+  auto load_conn = [&](int64_t t, int4& nb4, unsigned& fi4, int& cf) {
     const int64_t kk = t * kTileE + e;
+    cf = 0;
     if (t < c1 && kk < m.K) {
       nb4 = reinterpret_cast<const int4*>(m.nbr)[kk];
       fi4 = reinterpret_cast<const unsigned*>(m.finfo)[kk];
+      if (m.curved_flag) cf = m.curved_flag[kk];
     } else {
       nb4 = make_int4(-BC_PASSTHRU, -BC_PASSTHRU, -BC_PASSTHRU, -BC_PASSTHRU);
       fi4 = 0u;
@@ -170,7 +172,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   };
   int4 nbN;
   unsigned fiN;
-  load_conn(c0 + jb, nbN, fiN);
+  int cfN;
+  load_conn(c0 + jb, nbN, fiN, cfN);
   constexpr int kOut = (kTileE * MP + kThreads - 1) / kThreads;
   constexpr int kFQ = (S::NFQ + kWaves - 1) / kWaves;
 
@@ -218,6 +221,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const int ne = int(min<int64_t>(kTileE, m.K - k0));
     const bool valid = e < ne;
     const int nbr[4] = {nbN.x, nbN.y, nbN.z, nbN.w};
+    // tile elements of the curved set (bit e): their outputs and rate are the
+    // curved pass's
+    const unsigned cmask = unsigned(__ballot(cfN != 0)) & 0xffffu;
     __syncthreads();  // previous tile fully consumed (and prologue tables ready)
 
     // A. asynchronous loads: exterior traces (offsets precomputed), then the
@@ -272,7 +278,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       // (the geometry array is zero past the last element)
       for (int i = tid_t; i < kTileE * 25; i += kThreads) lds[S::oG + i] = m.geo32[tile * kTileE * 25 + i];
     }
-    load_conn(tile + Gx, nbN, fiN);  // next tile's connectivity, in flight meanwhile
+    load_conn(tile + Gx, nbN, fiN, cfN);  // next tile's connectivity, in flight meanwhile
     __builtin_amdgcn_s_waitcnt(0);
     gather_offsets(tile + Gx);
     __syncthreads();
@@ -478,7 +484,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       for (int i = 0; i < kOut; ++i) {
         const int o = min(tid_t + i * kThreads, kTileE * MP - 1);
         const int eo = o / MP, node = o - eo * MP;
-        okv[i] = (tid_t + i * kThreads < kTileE * MP) && node < Np && eo < ne;
+        okv[i] = (tid_t + i * kThreads < kTileE * MP) && node < Np && eo < ne &&
+                 !((cmask >> eo) & 1u);
         const int nd = node < Np ? node : Np - 1;
         float acc_s = 0.0f;
 #pragma unroll
@@ -515,7 +522,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       __syncthreads();
       for (int it = tid_t; it < kTileE * S::NF; it += kThreads) {
         const int eo = it / S::NF, i = it - eo * S::NF, f = i / Nfp;
-        if (eo >= ne) continue;
+        if (eo >= ne || ((cmask >> eo) & 1u)) continue;
         const int node = sFm[i];
         float qq[5];
 #pragma unroll
@@ -615,8 +622,20 @@ __global__ __launch_bounds__(256) void rate_kernel(DeviceMesh m, const float* __
   }
 }
 
-__global__ void finalize_kernel(RunScalars* run) {
-  const float rate = __uint_as_float(run->rate_bits);
+// one block of kRateParts threads (rates are non-negative, so the largest
+// float is the largest bit pattern)
+__global__ __launch_bounds__(kRateParts) void finalize_kernel(RunScalars* run) {
+  __shared__ unsigned wmax[kRateParts / 64];
+  unsigned b = run->rate_part[threadIdx.x];
+  run->rate_part[threadIdx.x] = 0u;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) b = max(b, unsigned(__shfl_xor(int(b), off)));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = b;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  unsigned bits = run->rate_bits;
+  for (int w = 0; w < kRateParts / 64; ++w) bits = max(bits, wmax[w]);
+  const float rate = __uint_as_float(bits);
   run->dt = run->fixed_dt > 0.0 ? run->fixed_dt : (rate > 0.0f) ? run->cfl / double(rate) : 0.0;
   if (run->bad && run->first_bad < 0) run->first_bad = run->step;
   run->rate_bits = 0u;
@@ -878,7 +897,7 @@ hipError_t launch_rate(const DeviceMesh& m, const float* q, RunScalars* run, hip
 }
 
 hipError_t launch_finalize(RunScalars* run, hipStream_t s) {
-  finalize_kernel<<<1, 1, 0, s>>>(run);
+  finalize_kernel<<<1, kRateParts, 0, s>>>(run);
   return hipGetLastError();
 }
 

@@ -34,12 +34,23 @@ struct DeviceMesh {
   const float* lghost = nullptr;
   // absorbing layer: damping rate per node [K][Np] (rhs -= sigma q'), or null
   const float* sigma = nullptr;
+  // [K] 1 for the elements of the curved set, or null: the stage kernels
+  // leave their outputs and their share of the time-step rate to the curved
+  // pass
+  const uint8_t* curved_flag = nullptr;
   int variant = 0;                  // stage kernel: 0 tile-cooperative, 1 role-specialized
   // 0: nodal strong form + LSERK4; 1: weak form with Gauss quadrature + RK2
   int scheme = 0;
   const float* qtab = nullptr;      // quadrature-scheme tables (scheme 1)
   Phys phys;
 };
+
+// Slots over which passes with many small blocks spread their time-step
+// rate maxima (one word would queue their atomics); the finalize kernel
+// folds them in.
+constexpr int kRateParts = 256;
+static_assert(kRateParts % 64 == 0 && (kRateParts & (kRateParts - 1)) == 0,
+              "whole wavefronts, and a mask picks the slot");
 
 // Device scalars of a run: time, step, CFL reduction and error flags.
 struct RunScalars {
@@ -51,6 +62,7 @@ struct RunScalars {
   int64_t first_bad;
   uint32_t rate_bits;
   uint32_t bad;
+  uint32_t rate_part[kRateParts];   // more rate maxima (ordered float bits), 0 when unused
 };
 
 enum StageMode : int { MODE_RHS = 0, MODE_STAGE = 1 };
@@ -78,7 +90,8 @@ hipError_t launch_spec_stage(const DeviceMesh& m, int mode, const float* q_in, f
 // run->rate_bits (as ordered float bits); flags non-physical traces.
 hipError_t launch_rate(const DeviceMesh& m, const float* q, RunScalars* run, hipStream_t s);
 
-// dt = cfl / rate; records the first non-physical step; clears the reduction.
+// dt = cfl / rate (the maximum of rate_bits and rate_part); records the first
+// non-physical step; clears the reduction.
 hipError_t launch_finalize(RunScalars* run, hipStream_t s);
 
 // t += dt; step += 1.

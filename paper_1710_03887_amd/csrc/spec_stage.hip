@@ -162,7 +162,8 @@ __device__ __forceinline__ void contraction_role(const DeviceMesh& m, const Tile
       const int ti = it - 1;
       const int64_t k0 = T(ti) * kTE;
       const int ne = int(min<int64_t>(kTE, m.K - k0));
-      const bool valid = e < ne;
+      // (elements of the curved set are left to the curved pass)
+      const bool valid = e < ne && !(m.curved_flag && m.curved_flag[k0 + e]);
       const float* sQ = lds + S::oSlot + (ti % kSlots) * S::slotFloats;
       const double* sV = reinterpret_cast<const double*>(sQ + S::qFloats);   // [16][9]
       const float* sD = lds + S::oD + (ti & 1) * S::dFloats;
@@ -461,7 +462,7 @@ __device__ __forceinline__ void surface_role(const DeviceMesh& m, const Tiles& T
       const int64_t k0 = T(it - 2) * kTE;
       const int ne = int(min<int64_t>(kTE, m.K - k0));
       const float* sQn = lds + S::oQn + (it & 1) * S::qFloats;
-      if (e < ne) {
+      if (e < ne && !(m.curved_flag && m.curved_flag[k0 + e])) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           const int ii = g + 4 * r;

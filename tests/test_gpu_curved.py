@@ -92,8 +92,8 @@ def test_rhs_parity_curved_ragged_and_all(N, n, x0):
 
 def test_stage_matches_rhs_and_clearing():
     """One LSERK stage equals q + b (a res + dt rhs) element by element (the
-    curved elements' residual is taken before the stage kernel rewrites it),
-    and clearing the curved set restores the straight-sided operator."""
+    stage kernel leaves the curved elements' residual and state to their own
+    pass), and clearing the curved set restores the straight-sided operator."""
     phys = euler.Physics()
     m, pair, geo, x_lib = _setup(3, phys)
     prim = gaussian_pulse(geo.x, 0.05 * phys.p0, 0.5, (0.6, 0.1, 0.0), phys.rho0, phys.p0,
