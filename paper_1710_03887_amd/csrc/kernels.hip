@@ -116,7 +116,12 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-template <int N, int MODE, bool MOVING, int PREC, bool DAMP>
+// EXTRA: bit 0 an absorbing layer (rhs -= sigma q'), bit 1 a curved set
+// (its elements' outputs and rate are left to the curved pass); plain meshes
+// run the kernel with neither.
+enum : int { EXTRA_DAMP = 1, EXTRA_CURVED = 2 };
+
+template <int N, int MODE, bool MOVING, int PREC, int EXTRA>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel(DeviceMesh m, const float* __restrict__ q_in,
                                                          float* __restrict__ q_out,
                                                          float* __restrict__ res,
@@ -126,6 +131,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                                                          int rate_out) {
   using S = Shape<N, PREC>;
   constexpr int Np = S::Np, Nfp = S::Nfp, ST = S::ST, MT = S::MT, AS = S::AS, MP = S::MP;
+  constexpr bool DAMP = (EXTRA & EXTRA_DAMP) != 0, CURVED = (EXTRA & EXTRA_CURVED) != 0;
   extern __shared__ float lds[];
   // row k of the FP32 operator is sA[k * AS + col] (LDS holds rows >= AROW0)
   const float* sA = S::A_LDS ? lds + S::oA - S::AROW0 * AS : m.Aop;
@@ -157,14 +163,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const int64_t c0 = ntiles * x / nX, c1 = ntiles * (x + 1) / nX;
 
   // connectivity of a lane's element, one tile ahead: 4 neighbours + packed
-  // (neighbour face | orientation << 2) bytes, and whether it is curved
+  // (neighbour face | orientation << 2) bytes, and (CURVED) whether the
+  // element is curved
   auto load_conn = [&](int64_t t, int4& nb4, unsigned& fi4, int& cf) {
     const int64_t kk = t * kTileE + e;
     cf = 0;
     if (t < c1 && kk < m.K) {
       nb4 = reinterpret_cast<const int4*>(m.nbr)[kk];
       fi4 = reinterpret_cast<const unsigned*>(m.finfo)[kk];
-      if (m.curved_flag) cf = m.curved_flag[kk];
+      if (CURVED) cf = m.curved_flag[kk];
     } else {
       nb4 = make_int4(-BC_PASSTHRU, -BC_PASSTHRU, -BC_PASSTHRU, -BC_PASSTHRU);
       fi4 = 0u;
@@ -221,9 +228,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const int ne = int(min<int64_t>(kTileE, m.K - k0));
     const bool valid = e < ne;
     const int nbr[4] = {nbN.x, nbN.y, nbN.z, nbN.w};
-    // tile elements of the curved set (bit e): their outputs and rate are the
-    // curved pass's
-    const unsigned cmask = unsigned(__ballot(cfN != 0)) & 0xffffu;
+    // (CURVED) the tile's curved elements, bit e: their outputs and rate are
+    // the curved pass's
+    const unsigned cmask = CURVED ? unsigned(__ballot(cfN != 0)) & 0xffffu : 0u;
     __syncthreads();  // previous tile fully consumed (and prologue tables ready)
 
     // A. asynchronous loads: exterior traces (offsets precomputed), then the
@@ -485,7 +492,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         const int o = min(tid_t + i * kThreads, kTileE * MP - 1);
         const int eo = o / MP, node = o - eo * MP;
         okv[i] = (tid_t + i * kThreads < kTileE * MP) && node < Np && eo < ne &&
-                 !((cmask >> eo) & 1u);
+                 !(CURVED && ((cmask >> eo) & 1u));
         const int nd = node < Np ? node : Np - 1;
         float acc_s = 0.0f;
 #pragma unroll
@@ -522,7 +529,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       __syncthreads();
       for (int it = tid_t; it < kTileE * S::NF; it += kThreads) {
         const int eo = it / S::NF, i = it - eo * S::NF, f = i / Nfp;
-        if (eo >= ne || ((cmask >> eo) & 1u)) continue;
+        if (eo >= ne || (CURVED && ((cmask >> eo) & 1u))) continue;
         const int node = sFm[i];
         float qq[5];
 #pragma unroll
@@ -680,12 +687,13 @@ __global__ void prim_kernel(DeviceMesh m, const float* __restrict__ in, float* _
 template <int N, int MODE, bool MOVING, int PREC>
 hipError_t set_lds_limit() {
   const int lds = int(Shape<N, PREC>::total * sizeof(float));
-  hipError_t e = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&stage_kernel<N, MODE, MOVING, PREC, false>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<N, MODE, MOVING, PREC, true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  const void* fns[4] = {reinterpret_cast<const void*>(&stage_kernel<N, MODE, MOVING, PREC, 0>),
+                        reinterpret_cast<const void*>(&stage_kernel<N, MODE, MOVING, PREC, 1>),
+                        reinterpret_cast<const void*>(&stage_kernel<N, MODE, MOVING, PREC, 2>),
+                        reinterpret_cast<const void*>(&stage_kernel<N, MODE, MOVING, PREC, 3>)};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 4 && e == hipSuccess; ++i)
+    e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   return e;
 }
 
@@ -698,7 +706,7 @@ hipError_t stage_prepare_prec(int* blocks_per_cu) {
   if (e != hipSuccess) return e;
   int nb = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &nb, reinterpret_cast<const void*>(&stage_kernel<N, MODE_STAGE, true, PREC, false>), kThreads,
+      &nb, reinterpret_cast<const void*>(&stage_kernel<N, MODE_STAGE, true, PREC, 0>), kThreads,
       Shape<N, PREC>::total * sizeof(float));
   if (e != hipSuccess) return e;
   *blocks_per_cu = std::max(nb, 1);
@@ -716,12 +724,17 @@ void stage_launch(int blocks, hipStream_t s, const DeviceMesh& m, const float* q
                   float* res, float* out, float a, float b, double c, double t_host,
                   double dt_host, RunScalars* run, int rate_out) {
   const size_t lds = size_t(Shape<N, PREC>::total) * sizeof(float);
-  if (m.sigma)
-    stage_kernel<N, MODE, MOVING, PREC, true><<<blocks, kThreads, lds, s>>>(
-        m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out);
-  else
-    stage_kernel<N, MODE, MOVING, PREC, false><<<blocks, kThreads, lds, s>>>(
-        m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out);
+  const int extra = (m.sigma ? EXTRA_DAMP : 0) | (m.curved_flag ? EXTRA_CURVED : 0);
+#define DG_STAGE_EXTRA(X)                                                          \
+  stage_kernel<N, MODE, MOVING, PREC, X><<<blocks, kThreads, lds, s>>>(            \
+      m, q_in, q_out, res, out, a, b, c, t_host, dt_host, run, rate_out)
+  switch (extra) {
+    case 0: DG_STAGE_EXTRA(0); break;
+    case 1: DG_STAGE_EXTRA(1); break;
+    case 2: DG_STAGE_EXTRA(2); break;
+    default: DG_STAGE_EXTRA(3); break;
+  }
+#undef DG_STAGE_EXTRA
 }
 
 template <int N, int PREC>
