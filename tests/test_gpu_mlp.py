@@ -65,9 +65,13 @@ def test_forward_fp32_and_bf16_match_oracle():
         assert np.abs(Yd.cpu().numpy() - Y_or[:B]).max() / np.abs(Y_or).max() < 3e-2
 
 
-def test_gradient_matches_oracle():
+@pytest.mark.parametrize("rows", [777, 4100])
+def test_gradient_matches_oracle(rows):
+    """Loss and gradient against the FP64 oracle; 777 rows split the
+    weight-gradient products into two chunks (the last one ragged), 4,100
+    rows into the most chunks (eight)."""
     p = _params(2)
-    X, Y = _data(777, 2)
+    X, Y = _data(rows, 2)
     Xf, Yf = X.astype(np.float32).astype(np.float64), Y.astype(np.float32).astype(np.float64)
     L_or, g_or = omlp.grad(p.astype(np.float64), Xf, Yf)
     m = dg.dg_mlp_create(p)
