@@ -100,11 +100,13 @@ def equispaced_barycentric(N):
     return np.array(pts, dtype=np.float64) / max(N, 1)
 
 
-def warp_blend_nodes(N):
-    """Reference coordinates [Np, 3] of the order-N warp-and-blend nodes."""
+def warp_blend_nodes(N, alpha=None):
+    """Reference coordinates [Np, 3] of the order-N warp-and-blend nodes
+    (blend parameter alpha, by default the optimized value of the order)."""
     if N < 1:
         raise ValueError("N must be >= 1")
-    alpha = ALPHA_OPT[N - 1] if N <= len(ALPHA_OPT) else 1.0
+    if alpha is None:
+        alpha = ALPHA_OPT[N - 1] if N <= len(ALPHA_OPT) else 1.0
     lam = equispaced_barycentric(N)
     X = lam @ EQ_VERTS
     shift = np.zeros_like(X)
