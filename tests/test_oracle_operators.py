@@ -107,3 +107,49 @@ def test_discrete_divergence_theorem(N):
         rhs = sum(nparam[f, a] * (ref.Emass[f].sum(axis=0) @ u[ref.Fmask[f]])
                   for f in range(4))
         assert abs(lhs - rhs) < 1e-11 * (1 + abs(lhs))
+
+
+def _node_permutation(rst, sig):
+    """Node permutation induced by the vertex permutation sig of the
+    reference tetrahedron (vertices (-1,-1,-1), (1,-1,-1), (-1,1,-1),
+    (-1,-1,1)): node n goes to the node whose barycentric coordinates are
+    n's with vertex v's coordinate moved to vertex sig[v]; None if the node
+    set is not mapped onto itself."""
+    lam = np.stack([-(1 + rst.sum(1)) / 2, (1 + rst[:, 0]) / 2, (1 + rst[:, 1]) / 2,
+                    (1 + rst[:, 2]) / 2], 1)
+    tgt = np.empty_like(lam)
+    tgt[:, list(sig)] = lam
+    d = np.abs(tgt[:, None, :] - lam[None, :, :]).max(2)
+    p = d.argmin(1)
+    return p if (d[np.arange(len(p)), p] < 1e-12).all() else None
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
+def test_operators_follow_tetrahedron_symmetry(N):
+    """The reference tetrahedron is mapped onto itself by its 24 vertex
+    permutations (affine maps of unit determinant magnitude), the Warp &
+    Blend node set with it (Section 2.1), so the operators are tied to each
+    other: swapping vertices 2 and 3 swaps r and s, hence Ds(i, j) =
+    Dr(p(i), p(j)) for the induced node permutation p (Dt likewise with
+    vertices 2 and 4); and a permutation taking face f onto face 0 carries
+    face f's LIFT columns onto face 0's.  A derivative taken along the wrong
+    coordinate, a sign, or a face mask of the wrong face breaks these.  The
+    face relation holds up to the rounding of the monomial construction
+    (largest at N = 5, 3e-8 of max |LIFT|)."""
+    ref = RefElement(N)
+    perms = [_node_permutation(ref.rst, s) for s in __import__("itertools").permutations(range(4))]
+    assert all(p is not None for p in perms)                  # the node set is symmetric
+    for D, sig in ((ref.Ds, (0, 2, 1, 3)), (ref.Dt, (0, 3, 2, 1))):
+        p = _node_permutation(ref.rst, sig)
+        np.testing.assert_allclose(D, ref.Dr[np.ix_(p, p)], rtol=0, atol=1e-9 * np.abs(ref.Dr).max())
+    Fm = np.asarray(ref.Fmask).reshape(4, ref.Nfp)
+    on0 = -np.ones(ref.Np, int)
+    on0[Fm[0]] = np.arange(ref.Nfp)
+    L = ref.LIFT
+    for f in range(4):
+        best = np.inf
+        for p in perms:
+            t = on0[p[Fm[f]]]
+            if (t >= 0).all():
+                best = min(best, np.abs(L[:, f * ref.Nfp:(f + 1) * ref.Nfp] - L[p][:, t]).max())
+        assert best <= 1e-7 * np.abs(L).max(), (f, best)
