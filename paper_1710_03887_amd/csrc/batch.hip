@@ -129,8 +129,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(4)))
   const Phys& P = L.phys;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int e = lane & 15, g = lane >> 4;
-  const bool member = e < L.members;
+  const int e = lane & 15;
   // this wavefront's copy of its element's state [5][Np][16] (staged form)
   float* sQ = lds + S::total + wave * S::slot;
 
