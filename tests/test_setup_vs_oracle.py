@@ -116,6 +116,14 @@ def test_setup_errors():
     with pytest.raises(dg.DGError) as e:
         dg.dg_mesh_setup(m["xyz"], m["EToV"], tag, 2, host_only=True)
     assert e.value.code == dg.DG_EINVAL
+    with pytest.raises(dg.DGError, match="K must be positive") as e:     # empty mesh
+        dg.dg_mesh_setup(m["xyz"][:0], m["EToV"][:0], m["bc"][:0], 2, host_only=True)
+    assert e.value.code == dg.DG_EINVAL
+    # element 0 repeated: each of its faces is shared by three elements
+    cat = lambda a: np.concatenate([a, a[:1]])
+    with pytest.raises(dg.DGError, match="more than two") as e:
+        dg.dg_mesh_setup(cat(m["xyz"]), cat(m["EToV"]), cat(m["bc"]), 2, host_only=True)
+    assert e.value.code == dg.DG_EMESH
     ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], 2, host_only=True)
     import ctypes
     from paper_1710_03887_amd import _lib
