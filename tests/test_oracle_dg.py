@@ -307,3 +307,43 @@ def test_printed_values():
         if pa.startswith("_"):
             continue
         assert abs(100 * float(pa) / pu["atmosphere_Pa"] - pct) < 5e-4 * pct
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+def test_dt_rule_is_stable_with_margin(N):
+    """The time-step rule is a choice (the paper gives none), but two facts
+    bound it.  Linearized about the ambient state (central differences; the
+    Lax-Friedrichs speed's kink at u = 0 multiplies a jump that vanishes
+    there), the semi-discrete operator J of the box with characteristic
+    faces has its spectrum in the closed left half plane, the energy
+    stability of the upwind-type flux; and dt at CFL 0.5 puts every dt
+    lambda inside the stability region |R(z)| <= 1 of the five-stage scheme
+    (R from its coefficients, Appendix A, Eq. 12).  The largest stable CFL
+    lies between 1 and 4 at every order (observed 1.81, 2.10, 2.29, 2.44 at
+    N = 2..5): the (N+1)^2 Fscale (|u| + c) scaling tracks the spectral
+    radius, so the margin does not shrink with N (with (N+1) instead, CFL
+    0.5 is unstable at N = 4)."""
+    mesh = make_mesh(N, box_kuhn(1, jitter=0.05, seed=1))
+    phys = euler.Physics()
+    q0 = uniform_state(mesh, phys)
+    n, eps = q0.size, 1e-6
+    J = np.empty((n, n))
+    for j in range(n):
+        d = np.zeros(n)
+        d[j] = eps
+        d = d.reshape(q0.shape)
+        J[:, j] = ((euler.rhs(mesh, q0 + d, 0.0, phys) - euler.rhs(mesh, q0 - d, 0.0, phys))
+                   / (2 * eps)).ravel()
+    lam = np.linalg.eigvals(J)
+    assert lam.real.max() <= 1e-9 * np.abs(lam).max()
+
+    def amp(cfl):
+        z = cfl * timestep.stable_dt(mesh, q0, phys, 1.0) * lam
+        y, res = np.ones_like(z), np.zeros_like(z)
+        for a, b in zip(timestep.A, timestep.B):   # the scheme on y' = lambda y
+            res = a * res + z * y
+            y = y + b * res
+        return np.abs(y).max()
+
+    assert amp(0.5) <= 1 + 1e-9
+    assert amp(1.0) <= 1 + 1e-9 and amp(4.0) > 1 + 1e-9
