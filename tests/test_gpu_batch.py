@@ -212,3 +212,39 @@ def test_autotuners_keep_state_and_use_cache(setup, tmp_path):
     assert bpc >= 1 and torch.equal(qd, before)
     assert dg.dg_autotune(pair.ctx, qd, r, cache) == bpc
     assert len(open(cache).read().splitlines()) == 2
+
+
+@pytest.mark.timeout(600)
+def test_full_size_members_match_single_solves():
+    """The ensemble at its full size, in the launch shape the benchmark uses
+    (the autotuner's): the box, sphere and half domains at 49,536, 80,370
+    and 31,980 tets, N = 3, 16 members each, one launch per stage.  After 3
+    steps the members at 0.1 %, 1.2 % and 10 % p0 of every geometry match
+    single solves of the same geometry and amplitude (the library path the
+    full-size and 100-step tests pin to the oracle) within the same 1e-5
+    bar, with the same end time."""
+    sizes = (("box", 50_000, 49_536), ("sphere", 80_000, 80_370), ("half", 30_000, 31_980))
+    geoms = [trumpet_domain(kind, n) for kind, n, _ in sizes]
+    assert [len(g["EToV"]) for g in geoms] == [k for _, _, k in sizes]
+    pairs = [Pair(m, N, _phys(AMPS[0])) for m in geoms]
+    starts = [_start_state(p) for p in pairs]
+    b = dg.dg_batch_create([p.ctx for p in pairs], 16)
+    q = [_to_batch(p, s) for p, s in zip(pairs, starts)]
+    res = [torch.zeros_like(x) for x in q]
+    bpc, waves = dg.dg_batch_autotune(b, q, res, None)
+    print(f"launch shape: {bpc} blocks per CU, {waves} wavefronts per block")
+    amps = np.broadcast_to(AMPS, (3, 16))
+    t = dg.dg_batch_run(b, q, res, amps, 3, 0.5, np.full((3, 16), T_START))
+    torch.cuda.synchronize()
+    for g, G in enumerate(geoms):
+        for e in (0, 8, 15):
+            ctx = dg.dg_mesh_setup(G["xyz"], G["EToV"], G["bc"], N, p0=P0, inflow_amp=AMPS[e],
+                                   inflow_alpha=ALPHA)
+            qd = pairs[g].to_device(starts[g])
+            r1 = torch.zeros_like(qd)
+            t1, _ = dg.dg_run(ctx, qd, r1, 3, 0.5, T_START)
+            assert abs((t[g, e] - T_START) / (t1 - T_START) - 1) < 1e-6
+            err = norms.rel_l2_pressure(pairs[g].mesh, _member(pairs[g], q[g], e),
+                                        pairs[g].from_device(qd), pairs[g].phys)
+            print(f"{KINDS[g]} member {e} ({AMPS[e] / P0:.3%} p0): rel L2 {err:.2e}")
+            assert err < 1e-5, (g, e, err)
