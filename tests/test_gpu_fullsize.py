@@ -50,3 +50,69 @@ def test_rhs_parity_full_size_trumpet():
         print(f"precision {precision}: rhs rel L2 {err:.3e} over {pair.mesh.K} elements", flush=True)
         assert err < tol
         assert_nodewise(r_gpu, r_or, pair.bc, node_tol, f"precision {precision}")
+
+
+@pytest.mark.timeout(400)
+def test_learned_rhs_full_size_trumpet():
+    """The learned closure at the same full size: the outer box's faces of
+    the 207,900-tet trumpet tagged learned, a random network (output layer
+    damped, as in the small cases); the state of the test above plus a
+    second bump that reaches the x = 1.8 wall and part of the side walls.
+    On the elements with a learned face the right-hand side meets the small
+    cases' bar for a BF16 network inside an FP32 right-hand side (2e-3
+    relative L2) and differs from the characteristic ghost's by more than
+    ten times that error (the network path is taken); every other element
+    meets the FP32 node-by-node bar (relative to each variable's largest
+    value over the mesh)."""
+    from oracle import mlp as omlp
+    from workloads import BC_LEARNED, BC_OUTFLOW_CHAR
+    from workloads.mlp_init import init_params
+    from helpers import nodewise_errors
+    m = trumpet_domain("box", 200_000)
+    bc = m["bc"].copy()
+    bc[bc == BC_OUTFLOW_CHAR] = BC_LEARNED
+    m = dict(m, bc=bc)
+    phys = euler.Physics(amp=0.1 / 1.4, alpha=ALPHA)
+    pair = Pair(m, 4, phys)
+    assert pair.mesh.K == 207_900
+    lrn = (pair.mesh.bc == BC_LEARNED).any(axis=1)
+    x = pair.mesh.x
+    prim = gaussian_pulse(x, 0.05 * phys.p0, 0.2, (1.1, 0.1, 0.0), phys.rho0, phys.p0, phys.gamma)
+    wall = gaussian_pulse(x, 0.05 * phys.p0, 0.25, (1.55, 0.2, 0.0), phys.rho0, phys.p0,
+                          phys.gamma)
+    prim[..., 0] += wall[..., 0] - phys.rho0
+    prim[..., 4] += wall[..., 4] - phys.p0
+    prim[..., 2] += 0.02 * np.exp(-((x[..., 0] - 1.2) ** 2) / 0.3)
+    q = euler.initial_state(prim, phys.gamma)
+    t_peak = np.pi / ALPHA
+    p = init_params(5).astype(np.float32)
+    p[128 * 78 + 128 + 128 * 128 + 128:] *= 0.05
+    net = dg.dg_mlp_create(p)
+    norm = 0.0
+    dg.dg_set_learned_bc(pair.ctx, net, norm, 1e-4, 1.0)
+    qd = pair.to_device(q)
+    res = torch.zeros_like(qd)
+    dg.dg_autotune(pair.ctx, qd, res)
+    rd = torch.empty_like(qd)
+    dg.dg_rhs(pair.ctx, qd, rd, t_peak)
+    torch.cuda.synchronize()
+    r_gpu = pair.rates_from_device(rd)
+    closure = omlp.closure(p.astype(np.float64), phys, norm, (2e-4, 0.5))
+    r_or = euler.rhs(pair.mesh, q, t_peak, phys, learned=closure)
+    r_char = euler.rhs(pair.mesh, q, t_peak, phys,
+                       learned=lambda qm, n: euler.ghost_state(euler.OUTFLOW_CHAR, qm, n, phys,
+                                                               t_peak))
+    w = pair.mesh.J[lrn][:, None, None]
+
+    def l2(a, b):      # Jacobian-weighted nodal L2 over the elements with a learned face
+        a, b = a[lrn], b[lrn]
+        return float(np.sqrt((w * (a - b) ** 2).sum() / (w * b ** 2).sum()))
+
+    err = l2(r_gpu, r_or)
+    sep = l2(r_char, r_or)
+    print(f"{lrn.sum()} elements with a learned face: rel L2 {err:.2e}, learned vs char {sep:.2e}")
+    assert err < 2e-3
+    assert sep > 10 * err
+    dn = nodewise_errors(r_gpu, r_or, {"rest": np.nonzero(~lrn)[0]})["rest"]
+    print(f"other elements: node-by-node max error / max |rhs| per variable {dn}")
+    assert (dn < 1e-5).all()
