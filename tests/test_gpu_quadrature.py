@@ -133,3 +133,69 @@ def test_scheme_restrictions():
     with pytest.raises(dg.DGError):
         dg.dg_batch_create([pair.ctx], 4)
     assert dg.dg_autotune(pair.ctx, q, torch.zeros_like(q)) == 0
+
+
+def _submesh_rhs(mesh, sample, N, q, t, phys):
+    """The quadrature oracle's right-hand side of the elements `sample` of
+    the mesh m, computed on the sub-mesh of those elements and their face
+    neighbours: an element's right-hand side depends only on its own state
+    and its neighbours' traces, so the neighbours' other faces may take any
+    tag (pass-through here).  Returns rhs[len(sample), 5, Np]."""
+    sample = np.asarray(sample)
+    nb = mesh.EToE[sample].ravel()
+    S = np.unique(np.concatenate([sample, nb[nb >= 0]]))
+    inS = np.zeros(mesh.K, dtype=bool)
+    inS[S] = True
+    # the oracle mesh's arrays, already positively oriented (its face order)
+    bc = mesh.bc[S].copy()
+    cut = (mesh.EToE[S] >= 0) & ~inS[np.maximum(mesh.EToE[S], 0)]
+    bc[cut] = BC_PASSTHRU
+    sub = Mesh(ref_of(N), mesh.xyz[S].copy(), mesh.EToV[S].copy(), bc)
+    r = QuadScheme(sub).rhs(q[S], t, phys)
+    return r[np.searchsorted(S, sample)]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("N", [1, 2])
+def test_rhs_parity_full_size_trumpet_sampled(N):
+    """The quadrature scheme at the size the benchmark times it (the
+    trumpet in the box, 207,900 tets, N = 1 and 2; the scheme has one launch
+    shape): one right-hand side on the GPU against the oracle on a sample of
+    elements -- the last tile, 2,000 random elements and up to 200 with a
+    face of each boundary tag -- with the oracle evaluated on the sub-mesh
+    of the sample and its neighbours (its tables for the whole mesh take
+    minutes of CPU; the sub-mesh result equals the whole mesh's exactly).
+    Same bars as the small cases: 5e-6 relative L2 (Jacobian-weighted nodal
+    norm over the sample) and 3e-5 node by node."""
+    phys = euler.Physics(amp=0.1 / 1.4)
+    m = trumpet_domain("box", 200_000)
+    ref = ref_of(N)
+    mesh = Mesh(ref, m["xyz"], m["EToV"], m["bc"])
+    assert mesh.K == 207_900
+    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, quadrature=True, **phys_kwargs(phys))
+    perm = node_perm(ctx, ref)
+    prim = gaussian_pulse(mesh.x, 0.05 * phys.p0, 0.3, (0.9, 0.05, 0.0), phys.rho0, phys.p0,
+                          phys.gamma)
+    prim[..., 1] += 0.02 * np.sin(np.pi * mesh.x[..., 1])
+    q = euler.initial_state(prim, phys.gamma)
+    qd = torch.tensor((q - phys.q0[None, :, None])[:, :, perm], dtype=torch.float32,
+                      device="cuda").contiguous()
+    rd = torch.full_like(qd, float("nan"))
+    dg.dg_rhs(ctx, qd, rd, 0.2)
+    torch.cuda.synchronize()
+    a = rd.double().cpu().numpy()
+    got = np.empty_like(a)
+    got[:, :, perm] = a
+    rng = np.random.default_rng(7)
+    picks = [rng.choice(mesh.K, 2000, replace=False), np.arange(mesh.K - 16, mesh.K)]
+    for tag in np.unique(mesh.bc[mesh.bc > 0]):
+        rows = np.nonzero((mesh.bc == tag).any(axis=1))[0]
+        picks.append(rng.choice(rows, min(200, rows.size), replace=False))
+    sample = np.unique(np.concatenate(picks))
+    r_or = _submesh_rhs(mesh, sample, N, q, 0.2, phys)
+    g = got[sample]
+    w = mesh.J[sample][:, None, None]
+    err = float(np.sqrt((w * (g - r_or) ** 2).sum() / (w * r_or ** 2).sum()))
+    print(f"N={N}: {sample.size} sampled elements, rhs rel L2 {err:.3e}")
+    assert err < 5e-6
+    assert_nodewise(g, r_or, mesh.bc[sample], 3e-5, f"quadrature full size N={N}")
