@@ -36,17 +36,25 @@ def _state(pair, amp, width, center, flow=0.0):
     return euler.initial_state(prim, phys.gamma)
 
 
-@pytest.mark.parametrize("case", ["box_n3_moving", "trumpet_n4"])
+@pytest.mark.parametrize("case", ["box_n3_moving", "trumpet_n4", "trumpet_full_n4"])
 def test_probe_sample_parity(case):
+    """trumpet_full_n4: the benchmark's mesh (207,900 tets) with its sensor
+    points added to the random ones."""
+    extra = np.zeros((0, 3))
     if case == "box_n3_moving":
         phys = euler.Physics(u0=(0.05, -0.02, 0.01))
         pair = Pair(box_kuhn(3, jitter=0.05, seed=4), 3, phys)
         q = _state(pair, 0.1, 0.4, (0.1, 0.0, -0.1), flow=0.03)
     else:
         phys = euler.Physics(amp=0.1 / 1.4)
-        pair = Pair(trumpet_domain("box", 3000), 4, phys)
+        m = trumpet_domain("box", 200_000 if case == "trumpet_full_n4" else 3000)
+        pair = Pair(m, 4, phys)
         q = _state(pair, 0.05, 0.3, (0.9, 0.05, 0.0), flow=0.02)
-    pts = _inside_points(pair.mesh, 30, 7)
+        if case == "trumpet_full_n4":
+            from paper_1710_03887_amd.sensors import sensor_points
+            assert pair.mesh.K == 207_900
+            extra = sensor_points(m)
+    pts = np.concatenate([_inside_points(pair.mesh, 30, 7), extra])
     elem, rst = probes.locate(pair.mesh, pts)
     p_or = probes.sample(pair.mesh, q, elem, probes.weights(pair.mesh.ref, rst), phys)
     e_lib = dg.dg_probe_setup(pair.ctx, pts)
