@@ -124,7 +124,10 @@ typedef struct dg_mesh_desc {
  * and 3), face matching, nodes, reference operators and affine geometry in
  * FP64 (Appendix A, Eqs. 9-11), then upload to the current HIP device.
  * Synchronous.  Host arrays are copied.  Errors: DG_EINVAL, DG_EMESH,
- * DG_ENOMEM, DG_EHIP; *out is NULL on failure.
+ * DG_ENOMEM, DG_EHIP; *out is NULL on failure.  Largest mesh: K x 5 x Np
+ * values (and learned faces x 5 x Np) at most 2^31 - 1, i.e. 12,271,335
+ * elements at N = 4 and 7,669,584 at N = 5 (the stage kernel's state
+ * offsets are 32-bit); larger meshes are rejected with DG_EINVAL.
  */
 int dg_mesh_setup(const dg_mesh_desc* d, void* stream, dg_ctx** out);
 

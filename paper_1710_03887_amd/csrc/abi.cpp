@@ -152,6 +152,8 @@ int build_device(dg_ctx* c, hipStream_t s) {
   if ((rc = upload(c, nbr.data(), nbr.size(), &dN, s))) return rc;
   if ((rc = upload(c, finfo.data(), finfo.size(), &dFi, s))) return rc;
   if ((rc = upload<float>(c, nullptr, size_t(K) * 5 * Np, &c->qbuf, s))) return rc;
+  if (int64_t(c->lface_host.size()) > INT32_MAX / (5LL * Np))
+    return fail(c, DG_EINVAL, "learned faces x 5 x Np exceeds 2^31 - 1 (32-bit trace offsets)");
   if (!c->lface_host.empty()) {
     int32_t* dLf;
     float* dGh;
@@ -255,6 +257,11 @@ int dg_mesh_setup(const dg_mesh_desc* d, void* stream, dg_ctx** out) {
   if (!d || !d->xyz || !d->EToV || !d->bc) return fail(nullptr, DG_EINVAL, "null mesh array");
   if (d->N < 1 || d->N > 5) return fail(nullptr, DG_EINVAL, "N must be in 1..5");
   if (d->K <= 0) return fail(nullptr, DG_EINVAL, "K must be positive");
+  // the tile-cooperative stage kernel forms its exterior-trace offsets
+  // (element x 5 Np + node) in 32 bits
+  const int64_t state_len = 5LL * (d->N + 1) * (d->N + 2) * (d->N + 3) / 6;
+  if (d->K > INT32_MAX / state_len)
+    return fail(nullptr, DG_EINVAL, "K x 5 x Np exceeds 2^31 - 1 (32-bit state offsets)");
   if (d->precision != DG_FP32 && d->precision != DG_SPLIT_BF16)
     return fail(nullptr, DG_EINVAL, "unknown precision");
   if ((d->flags & ~(DG_SETUP_HOST_ONLY | DG_SETUP_QUADRATURE)) != 0)

@@ -124,8 +124,18 @@ def test_setup_errors():
     with pytest.raises(dg.DGError, match="more than two") as e:
         dg.dg_mesh_setup(cat(m["xyz"]), cat(m["EToV"]), cat(m["bc"]), 2, host_only=True)
     assert e.value.code == dg.DG_EMESH
-    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], 2, host_only=True)
+    # the largest mesh: K x 5 x Np values must fit the stage kernel's 32-bit
+    # offsets (12,271,335 elements at N = 4); checked before any array is
+    # read, so a descriptor with tiny arrays and K one past the limit shows it
     import ctypes
     from paper_1710_03887_amd import _lib
+    one = np.zeros(16)
+    d = _lib.dg_mesh_desc(N=4, precision=dg.DG_FP32, K=(2**31 - 1) // 175 + 1,
+                          xyz=one.ctypes.data, EToV=one.ctypes.data, bc=one.ctypes.data,
+                          gamma=1.4, rho0=1.0, p0=1 / 1.4, flags=1)
+    h = ctypes.c_void_p()
+    assert _lib._lib.dg_mesh_setup(ctypes.byref(d), None, ctypes.byref(h)) == dg.DG_EINVAL
+    assert b"exceeds" in _lib._lib.dg_last_error(None)
+    ctx = dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], 2, host_only=True)
     code = _lib._lib.dg_rhs(ctx.handle, ctypes.c_void_p(16), ctypes.c_void_p(16), 0.0, None)
     assert code == dg.DG_ENODEV
