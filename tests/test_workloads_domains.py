@@ -43,3 +43,24 @@ def test_domain_mesh_and_sensors(kind):
         assert tri_on.sum() > 0.5 * side.sum()
     elem, _ = probes.locate(mesh, sensor_points(m))
     assert (elem >= 0).all(), (kind, elem)
+
+
+def test_locality_order_brings_neighbours_close():
+    """The Z-order of element centroids is a permutation that keeps every
+    element and face tag, and brings face neighbours close in memory (the
+    median index distance between neighbours falls at least tenfold from
+    the generator's slice order)."""
+    from workloads import locality_order, reorder
+    m = trumpet_domain("box", 20_000)
+    p = locality_order(m)
+    assert np.array_equal(np.sort(p), np.arange(len(p)))
+    r = reorder(m, p)
+    ref = RefElement(1)
+    dist = []
+    for mm in (m, r):
+        mesh = Mesh(ref, mm["xyz"], mm["EToV"], mm["bc"])
+        k, f = np.nonzero(mesh.EToE >= 0)
+        dist.append(np.median(np.abs(mesh.EToE[k, f] - k)))
+        assert np.array_equal(np.bincount(np.ravel(mm["bc"])), np.bincount(np.ravel(m["bc"])))
+    print(f"median neighbour index distance: {dist[0]:.0f} -> {dist[1]:.0f}")
+    assert dist[1] * 10 <= dist[0]

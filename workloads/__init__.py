@@ -9,7 +9,8 @@ operators, geometry and state from them.
 from .meshes import (BC_INTERIOR, BC_OUTFLOW_CHAR, BC_PASSTHRU, BC_WALL,
                      BC_INFLOW, BC_LEARNED, box_kuhn, trumpet_domain)
 from .fields import gaussian_pulse, plane_wave, isentropic_vortex
+from .order import locality_order, reorder
 
 __all__ = ["BC_INTERIOR", "BC_OUTFLOW_CHAR", "BC_PASSTHRU", "BC_WALL",
            "BC_INFLOW", "BC_LEARNED", "box_kuhn", "trumpet_domain",
-           "gaussian_pulse", "plane_wave", "isentropic_vortex"]
+           "gaussian_pulse", "plane_wave", "isentropic_vortex", "locality_order", "reorder"]
