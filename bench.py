@@ -235,10 +235,13 @@ def time_batch(dg, torch, steps, warmup, kernel_iters, scale=1.0):
     """The ensemble: full box (50k), sphere of radius 1.5 (80k) and half
     domain (30k) around the trumpet, 16 pulse amplitudes log-spaced over
     0.1%-10% of p0 each, N = 3, FP32, launch shape from the autotuner."""
-    from workloads import trumpet_domain
+    from workloads import trumpet_domain, locality_order, reorder
     p0, alpha, N = 1.0 / 1.4, 2 * np.pi * 565.0 / 343.0, 3
     meshes = [trumpet_domain(kind, int(n * scale))
               for kind, n in (("box", 50_000), ("sphere", 80_000), ("half", 30_000))]
+    # elements in the Z-order of their centroids (the ensemble's 1 GB of
+    # state outgrows the last-level cache)
+    meshes = [reorder(m, locality_order(m)) for m in meshes]
     ctxs = [dg.dg_mesh_setup(m["xyz"], m["EToV"], m["bc"], N, gamma=1.4, rho0=1.0, p0=p0,
                              inflow_amp=0.0, inflow_alpha=alpha) for m in meshes]
     Ks, Np = [c.K for c in ctxs], ctxs[0].Np
